@@ -1,0 +1,95 @@
+// Device-side data layout of the SPH step: per-instance descriptors, workspace views and
+// kernel launchers shared by the runtime (runtime.hip) and the kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace sph {
+
+// Largest cell population the search walks; fuller cells raise the capacity error and
+// are skipped, so that a collapsed state cannot turn a sweep into an O(N^2) loop.
+constexpr int kMaxCell = 1024;
+constexpr int kWave = 64;
+constexpr int kDiagChunks = 64;  // diagnostics partial sums per instance
+
+enum : uint32_t { ERR_NONFINITE = 1u, ERR_DOMAIN = 2u, ERR_CAPACITY = 4u, ERR_INPUT = 8u };
+enum { KIND_FLUID = 0, KIND_WALL_INNER = 1, KIND_WALL_OUTER = 2 };
+enum { KERNEL_CUBIC = 0, KERNEL_WENDLAND = 1 };
+
+// Everything a kernel needs to know about one instance.  Lives in device memory; all
+// lanes of a wavefront always belong to the same instance (particle ranges are padded to
+// whole wavefronts), so the fields are read with scalar loads.
+struct InstDesc {
+    double lo[3], hi[3], L[3], halfL[3], edge[3];
+    double h, inv_h, cut2;      // cut2 = (2h)^2: pair test r^2 < cut2
+    double wnorm;               // kernel normalisation constant
+    double W0;                  // W(0)
+    double mass[2], inertia[2]; // per species; inertia = kappa_I m dx^2
+    double rho0, B;             // Tait: P = B ((rho/rho0)^7 - 1)
+    double eta, sigma_T, C_l;
+    int32_t n[3], periodic[3];
+    int32_t cf, kernel;
+    uint32_t cell_off, n_cells; // this instance's cells in the global cell range
+    uint32_t part_off, n_part;  // this instance's particles in the global particle range
+    uint32_t wave_off, n_waves; // this instance's wavefronts in particle-parallel launches
+};
+
+// Per-instance values that change between step calls (wall rotation).
+struct StepParams {
+    double cosw, sinw, Omega, pad;
+};
+
+// Device views of the workspace.  Particle arrays are in cell-sorted order; "cur" selects
+// the buffer holding the current state of the double-buffered arrays.
+struct DevState {
+    int precision;          // 0: FP64, 1: FP32-mixed
+    int n_inst;
+    int cur;                // buffer (0/1) holding the current state
+    uint32_t N, C, n_waves; // particles, cells, wavefronts over all instances
+    InstDesc *desc;
+    StepParams *steptab;
+    double *x[2], *v[2], *w[2];   // [3][N] each
+    uint32_t *id[2];              // global particle id
+    uint8_t *sk[2];               // bit 0 species, bits 1-2 kind
+    void *acc, *alpha;            // [3][N], float or double
+    void *aux;                    // [N][4]: V = m/rho, P/rho^2, 1/rho^2, V/S (0 if S = 0)
+    void *rhoP;                   // [N][2]: rho, P
+    uint32_t *key, *slot, *tmp, *pcell;
+    uint32_t *count, *start, *bsum;
+    uint32_t *cell_xyz;           // global cell rank -> packed (cx | cy << 10 | cz << 20)
+    uint32_t *rank_of_lin;        // cell_off + linear cell index -> global cell rank
+    uint32_t *err;
+    double *diag_part;            // [n_inst][kDiagChunks][14]
+    double *diag_out;             // [n_inst][7]
+};
+
+struct Launch {
+    int bs_density = 256, bs_force = 256, bs_stream = 256;
+};
+
+// Launchers (kernels.hip).  All enqueue on `st` and return hipGetLastError().
+// mode 0: load/initial evaluation (no kick or drift); mode 1: time step.
+hipError_t launch_keys(const DevState &d, const Launch &L, hipStream_t st, int mode,
+                       double kick, double dt);
+hipError_t launch_scan(const DevState &d, const Launch &L, hipStream_t st);
+hipError_t launch_scatter(const DevState &d, const Launch &L, hipStream_t st);
+hipError_t launch_reorder(const DevState &d, const Launch &L, hipStream_t st, int mode,
+                          double kick, double dt);
+hipError_t launch_density(const DevState &d, const Launch &L, hipStream_t st);
+hipError_t launch_force(const DevState &d, const Launch &L, hipStream_t st);
+hipError_t launch_load(const DevState &d, const Launch &L, hipStream_t st, const double *x,
+                       const double *v, const double *w, const uint8_t *species,
+                       const uint8_t *kind);
+hipError_t launch_read(const DevState &d, const Launch &L, hipStream_t st, double pend,
+                       double *x, double *v, double *w, double *rho, double *P, double *acc,
+                       double *alpha);
+hipError_t launch_diag(const DevState &d, const Launch &L, hipStream_t st, double pend);
+hipError_t launch_debug_keys(const DevState &d, const Launch &L, hipStream_t st,
+                             uint32_t *key_by_id, uint32_t *perm);
+hipError_t launch_debug_nbr(const DevState &d, const Launch &L, hipStream_t st, int phase,
+                            int64_t *row_ptr, int32_t *cols);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st);
+
+}  // namespace sph

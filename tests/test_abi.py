@@ -1,0 +1,141 @@
+"""Host-side checks of the C ABI: symbols, struct layout, validation (no GPU needed)."""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2405_03980_amd import _lib as L
+from paper_2405_03980_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sph4he.h")
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    names = L.header_symbols(HEADER)
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L._PROTOS), set(names) ^ set(L._PROTOS)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "sph4he.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(sph_params), offsetof(sph_params, dx),
+         offsetof(sph_params, lo), offsetof(sph_params, mass), offsetof(sph_params, kappa_I),
+         offsetof(sph_params, cell_factor), sizeof(sph_tuning));
+  return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    P = L.SphParams
+    want = [C.sizeof(P), P.dx.offset, P.lo.offset, P.mass.offset, P.kappa_I.offset,
+            P.cell_factor.offset, C.sizeof(L.SphTuning)]
+    assert got == want
+
+
+def _params(w, **kw):
+    d = dict(w.params)
+    d.update(kw)
+    return L.make_params(d, L.FP32_MIXED)
+
+
+def _ws_status(p, n=1000):
+    nb = C.c_size_t(0)
+    return L.lib().sph_workspace_bytes(C.byref(p), C.c_int64(n), C.byref(nb)), nb.value
+
+
+def test_params_init_defaults():
+    p = L.SphParams()
+    assert L.lib().sph_params_init(C.byref(p)) == L.OK
+    assert p.abi_version == L.ABI_VERSION and p.gamma == 7.0 and p.cell_factor == 1
+    assert p.kernel == L.KERNEL_WENDLAND_C2 and p.precision == L.FP32_MIXED
+
+
+def test_validation_rejects_bad_parameters():
+    w = I.make_cylinder(10)
+    assert _ws_status(_params(w))[0] == L.OK
+    assert _ws_status(_params(w, gamma=5.0))[0] == L.E_UNSUPPORTED
+    assert _ws_status(_params(w, h=-1.0))[0] == L.E_INVALID
+    assert _ws_status(_params(w, kappa_I=0.0))[0] == L.E_INVALID
+    assert _ws_status(_params(w, cell_factor=0))[0] == L.E_INVALID
+    assert _ws_status(_params(w, c0=float("nan")))[0] == L.E_INVALID
+    # periodic axis too short for the stencil: 2 cells of 2h
+    assert _ws_status(_params(I.make_box(4, h_factor=1.3)))[0] == L.E_INVALID
+    p = _params(w)
+    p.abi_version = 99
+    assert _ws_status(p)[0] == L.E_INVALID
+    p = _params(w)
+    p.precision = 5
+    assert _ws_status(p)[0] == L.E_INVALID
+    assert _ws_status(_params(w), n=0)[0] == L.E_INVALID
+
+
+def test_workspace_grows_with_particles():
+    w = I.make_cylinder(10)
+    p = _params(w)
+    a = _ws_status(p, 1000)[1]
+    b = _ws_status(p, 100000)[1]
+    assert 0 < a < b
+    p64 = L.make_params(w.params, L.FP64)
+    nb = C.c_size_t(0)
+    L.lib().sph_workspace_bytes(C.byref(p64), C.c_int64(100000), C.byref(nb))
+    assert nb.value > b
+
+
+@pytest.mark.parametrize("case", ["box", "cylinder", "cluster", "box_cf2", "cyl_cf3"])
+def test_grid_dims_agree_with_oracle(case):
+    w = {"box": I.config(0), "cylinder": I.make_cylinder(92), "cluster": I.make_cluster(6),
+         "box_cf2": I.make_box(14, cell_factor=2),
+         "cyl_cf3": I.make_cylinder(40, cell_factor=3)}[case]
+    dims = (C.c_int32 * 3)()
+    assert L.lib().sph_grid_dims(C.byref(L.make_params(w.params)), dims) == L.OK
+    on, _ = O.grid_dims(w.params)
+    assert list(dims) == list(on)
+
+
+def test_create_rejects_missing_workspace():
+    w = I.make_cylinder(10)
+    p = _params(w)
+    h = C.c_void_p()
+    st = L.lib().sph_create(C.byref(p), C.c_int64(w.n), None, C.c_size_t(0), None, C.byref(h))
+    assert st == L.E_WORKSPACE and not h.value
+    st = L.lib().sph_create(C.byref(p), C.c_int64(w.n), C.c_void_p(0x1001), C.c_size_t(1 << 40),
+                            None, C.byref(h))
+    assert st == L.E_WORKSPACE
+
+
+def test_batch_validation():
+    ws = I.make_batch(3, scale=0.02)
+    arr = (L.SphParams * 3)(*[L.make_params(w.params) for w in ws])
+    counts = (C.c_int64 * 3)(*[w.n for w in ws])
+    nb = C.c_size_t(0)
+    assert L.lib().sph_batch_workspace_bytes(3, arr, counts, C.byref(nb)) == L.OK
+    total = nb.value
+    singles = 0
+    for w in ws:
+        singles += _ws_status(L.make_params(w.params), w.n)[1]
+    assert total < singles
+    arr[1].precision = L.FP64
+    assert L.lib().sph_batch_workspace_bytes(3, arr, counts, C.byref(nb)) == L.E_INVALID
+    arr[1].precision = L.FP32_MIXED
+    counts[2] = 0
+    assert L.lib().sph_batch_workspace_bytes(3, arr, counts, C.byref(nb)) == L.E_INVALID
+
+
+def test_status_strings():
+    lib = L.lib()
+    for s in range(9):
+        assert lib.sph_status_str(s)
+    assert lib.sph_status_str(123) == b"unknown status"

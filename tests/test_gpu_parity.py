@@ -1,0 +1,261 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances: FP64 path 1e-12 per field; FP32-mixed path 1e-5 after one step and 1e-3
+after 100 steps (normwise relative, fluid particles; positions as displacement, pressure
+over the Tait stiffness B).  Cell lists and neighbour sets must match bit for bit when
+both sides see the same positions.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2405_03980_amd import _lib as L
+from paper_2405_03980_amd import inputs as I
+from tests._parity import field_errors
+
+pytestmark = pytest.mark.gpu
+
+FP64, MIXED = L.FP64, L.FP32_MIXED
+
+
+def _sim(w, prec, **tune):
+    from paper_2405_03980_amd import sim as S
+    s = S.simulation_from(w, precision=prec)
+    if tune:
+        s.set_tuning(**tune)
+    return s
+
+
+def _jitter_box(n=12, seed=1, amp=0.3, kernel=I.KERNEL_WENDLAND_C2, **kw):
+    w = I.make_box(n, kernel=kernel, **kw)
+    rng = np.random.default_rng(seed)
+    w.x = np.mod(w.x + rng.uniform(-amp, amp, size=w.x.shape) / n, 1.0)
+    w.v = w.v + rng.normal(0, 0.05, size=w.v.shape)
+    w.omega = rng.normal(0, 1.0, size=w.omega.shape)
+    return w
+
+
+CELL_CASES = {
+    "box4096": lambda: I.config(0),
+    "cylinder": lambda: I.make_cylinder(14),
+    "cluster": lambda: I.make_cluster(9),
+    "box_cf2": lambda: I.make_box(14, cell_factor=2),
+    "jitter": lambda: _jitter_box(13),
+}
+
+
+@pytest.mark.parametrize("case", list(CELL_CASES))
+def test_cells_bit_exact(case):
+    w = CELL_CASES[case]()
+    print(f"[cells] {case} n={w.n}", flush=True)
+    s = _sim(w, FP64)
+    key, perm, cs = s.debug_cells()
+    okey, operm, ocs = O.cells(w.params, w.x)
+    assert np.array_equal(key, okey)
+    assert np.array_equal(perm, operm)
+    assert np.array_equal(cs, ocs)
+    s.close()
+
+
+@pytest.mark.parametrize("case", ["box4096", "cylinder", "jitter", "box_cf2"])
+def test_neighbors_bit_exact(case):
+    w = CELL_CASES[case]()
+    print(f"[nbr] {case} n={w.n}", flush=True)
+    s = _sim(w, MIXED)
+    row, cols = s.debug_neighbors()
+    orow, ocols = O.neighbors(w.params, w.x)
+    assert np.array_equal(row, orow)
+    assert np.array_equal(cols, ocols)
+    s.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(FP64, 1e-12), (MIXED, 1e-5)])
+@pytest.mark.parametrize("case", ["box4096", "cylinder", "jitter"])
+def test_initial_fields(case, prec, tol):
+    w = CELL_CASES[case]()
+    print(f"[init] {case} prec={prec} n={w.n}", flush=True)
+    ref = O.State.from_workload(w)
+    s = _sim(w, prec)
+    out = s.read()
+    e = field_errors(out, ref, w)
+    print(e, flush=True)
+    for k in ("rho", "P", "acc", "alpha"):
+        assert e[k] < tol, (k, e[k])
+    assert np.array_equal(out["x"], w.x)
+    s.close()
+
+
+def test_box4096_fp64_20_steps():
+    w = I.config(0)
+    ref = O.State.from_workload(w)
+    ref.step(w.dt, w.Omega, w.steps)
+    s = _sim(w, FP64)
+    s.step(w.dt, w.Omega, w.steps)
+    e = field_errors(s.read(), ref, w)
+    print("box4096 fp64 20 steps", e, flush=True)
+    assert max(e.values()) < 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("prec,steps,tol", [(FP64, 100, 1e-12), (MIXED, 1, 1e-5), (MIXED, 100, 1e-3)])
+def test_cylinder_steps(prec, steps, tol):
+    w = I.make_cylinder(16, seed=(3980, 1))
+    print(f"[cyl] prec={prec} steps={steps} n={w.n}", flush=True)
+    ref = O.State.from_workload(w)
+    ref.step(1e-4, w.Omega, steps)
+    s = _sim(w, prec)
+    s.step(1e-4, w.Omega, steps)
+    e = field_errors(s.read(), ref, w)
+    print(e, flush=True)
+    for k in ("x", "v", "omega", "rho", "P"):
+        assert e[k] < tol, (k, e[k])
+    s.close()
+
+
+TERMS = {
+    "pressure": dict(eta=0.0, sigma_T=0.0, C_l=0.0),
+    "interfacial": dict(eta=0.0, sigma_T=3.0, C_l=0.0, c0=0.0),
+    "viscous": dict(eta=0.2, sigma_T=0.0, C_l=0.0, c0=0.0),
+    "friction": dict(eta=0.0, sigma_T=0.0, C_l=5.0, c0=0.0),
+}
+
+
+@pytest.mark.parametrize("prec,tol", [(FP64, 1e-12), (MIXED, 1e-5)])
+@pytest.mark.parametrize("term", list(TERMS))
+def test_term_isolation(term, prec, tol):
+    """Each pair term alone with O(1) coefficients, so a small term cannot hide under
+    the tolerance of the others."""
+    w = _jitter_box(12, seed=7)
+    w.params = dict(w.params, **TERMS[term])
+    if w.params["c0"] == 0.0:
+        w.params["c0"] = 1e-9
+    ref = O.State.from_workload(w)
+    s = _sim(w, prec)
+    e = field_errors(s.read(), ref, w)
+    print(term, prec, e, flush=True)
+    assert e["acc"] < tol and e["alpha"] < tol
+    s.close()
+
+
+def test_conservation_on_gpu():
+    w = I.make_cluster(10)
+    s = _sim(w, FP64)
+    P0, J0, E0 = s.diagnostics()
+    oP, oJ, oE = O.State.from_workload(w).diagnostics()
+    assert np.allclose(P0, oP, rtol=1e-13, atol=1e-18) and np.allclose(J0, oJ, rtol=1e-13, atol=1e-18)
+    s.step(1e-4, 0.0, 40)
+    P1, J1, E1 = s.diagnostics()
+    m = O.default_mass(w.params)[0]
+    scale = m * w.n * 0.05
+    assert np.abs(P1 - P0).max() < 1e-13 * scale
+    assert np.abs(J1 - J0).max() < 1e-13 * scale
+    s.close()
+
+
+@pytest.mark.parametrize("prec", [FP64, MIXED])
+def test_batch_equals_single(prec):
+    ws = I.make_batch(5, scale=0.05)
+    print("[batch] sizes", [w.n for w in ws], flush=True)
+    from paper_2405_03980_amd import sim as S
+    b = S.batch_from(ws, precision=prec)
+    Om = [w.Omega for w in ws]
+    b.step(1e-4, Om, 7)
+    out = b.read()
+    for i, w in enumerate(ws):
+        s = _sim(w, prec)
+        s.step(1e-4, w.Omega, 7)
+        o = s.read()
+        lo, hi = b.offsets[i], b.offsets[i + 1]
+        for k in ("x", "v", "omega", "rho", "P", "acc"):
+            assert np.array_equal(out[k][..., lo:hi], o[k]), (i, k)
+        s.close()
+    d = b.diagnostics()
+    assert d.shape == (5, 7)
+    b.close()
+
+
+@pytest.mark.parametrize("prec", [FP64, MIXED])
+def test_graph_replay_equals_eager(prec):
+    w = I.make_cylinder(12)
+    a = _sim(w, prec, use_graph=1)
+    b = _sim(w, prec, use_graph=0)
+    for it in range(3):
+        a.step(1e-4, 1.0, 6)
+        b.step(1e-4, 1.0, 6)
+        oa, ob = a.read(), b.read()
+        for k in oa:
+            assert np.array_equal(oa[k], ob[k]), (it, k)
+    a.close()
+    b.close()
+
+
+def test_resume_from_checkpoint():
+    """read_fields -> init_particles round trip: the fields come back unchanged, and a
+    resumed run tracks the oracle resumed from its own checkpoint.  (Resuming is not
+    bit-identical to continuing: velocity Verlet evaluates velocity-dependent forces at
+    the half-step velocity, the restart at the full-step one.)"""
+    from paper_2405_03980_amd import sim as S
+    # rigidly rotating box: positions move ~1e-3, far above their rounding (a resting
+    # cylinder moves ~1e-6, where one ulp of x is already 1e-10 of the displacement)
+    w = I.config(0)
+    half = _sim(w, FP64)
+    half.step(1e-4, 1.0, 10)
+    ck = half.read()
+    res = S.Simulation(w.params, w.n, precision=FP64)
+    res.init(ck["x"], ck["v"], ck["omega"], w.species, w.kind)
+    again = res.read()
+    for k in ("x", "v", "omega"):
+        assert np.array_equal(again[k], ck[k]), k
+    res.step(1e-4, 1.0, 10)
+    out = res.read()
+    ref = O.State.from_workload(w)
+    ref.step(1e-4, 1.0, 10)
+    ref = O.State(w.params, ref.x, ref.v, ref.omega, w.species, w.kind)
+    ref.step(1e-4, 1.0, 10)
+    e = field_errors(out, ref, w)
+    print("resume", e, flush=True)
+    for k in ("x", "v", "omega", "rho", "P"):
+        assert e[k] < 1e-12, (k, e[k])
+    for s in (half, res):
+        s.close()
+
+
+def test_nonfinite_input_is_reported():
+    w = I.make_cylinder(10)
+    w.v[0, 5] = np.nan
+    s = _sim(w, MIXED)
+    with pytest.raises(L.SphError) as e:
+        s.sync()
+    assert e.value.status == L.E_NONFINITE
+    s.close()
+
+
+def test_domain_exit_is_reported():
+    w = I.make_cluster(5)
+    w.v[0, 0] = 1e4  # leaves the open grid in one step
+    s = _sim(w, FP64)
+    s.step(1e-4, 0.0, 1)
+    with pytest.raises(L.SphError) as e:
+        s.read()
+    assert e.value.status == L.E_DOMAIN
+    s.close()
+
+
+def test_invalid_species_is_reported():
+    w = I.make_cylinder(10)
+    w.species[w.kind != I.FLUID] = 0   # walls must be viscous
+    s = _sim(w, MIXED)
+    with pytest.raises(L.SphError) as e:
+        s.sync()
+    assert e.value.status == L.E_INVALID
+    s.close()
+
+
+def test_step_before_init_is_a_state_error():
+    from paper_2405_03980_amd import sim as S
+    w = I.make_cylinder(10)
+    s = S.Simulation(w.params, w.n, precision=MIXED)
+    with pytest.raises(L.SphError) as e:
+        s.step(1e-4, 1.0, 1)
+    assert e.value.status == L.E_STATE
+    s.close()
