@@ -106,6 +106,9 @@ typedef struct {
     int32_t block_stream;   /* threads per block of the streaming kernels                 */
     int32_t use_graph;      /* 1: replay steps from a captured hipGraph (needs a non-null */
                             /* stream); 0: launch eagerly; -1: keep                        */
+    int32_t sweep;          /* FP32-mixed density/force sweeps: 1 one thread per particle; */
+                            /* 2 one workgroup per 2x2x2-cell brick staged in LDS (needs   */
+                            /* cell_factor 1 on every instance); 0: keep                   */
 } sph_tuning;
 
 typedef struct sph_sim sph_sim;      /* one SPH instance (opaque, host memory)            */

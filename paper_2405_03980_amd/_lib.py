@@ -38,7 +38,7 @@ class SphParams(C.Structure):
 
 class SphTuning(C.Structure):
     _fields_ = [("block_density", C.c_int32), ("block_force", C.c_int32),
-                ("block_stream", C.c_int32), ("use_graph", C.c_int32)]
+                ("block_stream", C.c_int32), ("use_graph", C.c_int32), ("sweep", C.c_int32)]
 
 
 # name -> (restype, argtypes)

@@ -79,20 +79,25 @@ __device__ __forceinline__ int cell_coord(const InstDesc *d, int a, double x, ui
     return (int)f;
 }
 
+// Minimum image along one axis, branch-free: halfL is +inf on bounded axes, so neither
+// correction applies there.
 __device__ __forceinline__ double min_img(const InstDesc *d, int a, double dd)
 {
-    if (d->periodic[a]) {
-        if (dd > d->halfL[a]) dd -= d->L[a];
-        else if (dd < -d->halfL[a]) dd += d->L[a];
-    }
-    return dd;
+    const double h = d->halfL[a], L = d->L[a];
+    double up = dd - L, dn = dd + L;
+    return dd > h ? up : (dd < -h ? dn : dd);
 }
 
-// (dx*dx + dy*dy) + dz*dz, each operation rounded: the neighbour test is bit-identical
-// to a plain double-precision evaluation in this order.
+// (dx*dx + dy*dy) + dz*dz with every product and sum rounded separately (no fused
+// multiply-add): the neighbour test is bit-identical to a plain double-precision
+// evaluation in this order.
 __device__ __forceinline__ double r2_exact(double a, double b, double c)
 {
-    return __dadd_rn(__dadd_rn(__dmul_rn(a, a), __dmul_rn(b, b)), __dmul_rn(c, c));
+#pragma clang fp contract(off)
+    double xx = a * a;
+    double yy = b * b;
+    double zz = c * c;
+    return (xx + yy) + zz;
 }
 
 __device__ __forceinline__ uint32_t morton3(uint32_t x, uint32_t y, uint32_t z)
@@ -383,14 +388,43 @@ struct Acc {
     }
 };
 
-// Density (kernel summation), unlike-neighbour kernel sum S and Tait EOS.
-template <typename R, bool KAHAN>
-__global__ void k_density(DevState s)
+// Writes rho, P and the per-particle factors of the force sweep from the kernel sums.
+// Inner wall and fluid: rho = m (W(0) + sum W); outer wall: rho0, P = 0 (kept at their
+// initial values); Tait EOS P = B ((rho/rho0)^7 - 1).
+template <typename R>
+__device__ __forceinline__ uint32_t density_finish(const DevState &s, const InstDesc *d, uint32_t p,
+                                                   int spi, int kind, double sumW, double S)
 {
-    PIdx t = map_thread(s);
-    if (!t.active) return;
-    const InstDesc *d = t.d;
-    const uint32_t p = t.p, N = s.N;
+    double mi = d->mass[spi];
+    double rho, P;
+    if (kind == KIND_WALL_OUTER) {
+        rho = d->rho0;
+        P = 0.0;
+    } else {
+        rho = mi * (d->W0 + sumW);
+        double r = rho / d->rho0;
+        double r2 = r * r;
+        P = d->B * ((r2 * r2) * (r2 * r) - 1.0);
+    }
+    double V = mi / rho;
+    double ir2 = 1.0 / (rho * rho);
+    R *aux = (R *)s.aux + 4 * (size_t)p;
+    aux[0] = (R)V;
+    aux[1] = (R)(P * ir2);
+    aux[2] = (R)ir2;
+    aux[3] = (R)(S > 0.0 ? V / S : 0.0);
+    R *rp = (R *)s.rhoP + 2 * (size_t)p;
+    rp[0] = (R)rho;
+    rp[1] = (R)P;
+    return (!isfinite(rho) || !isfinite(P)) ? (uint32_t)ERR_NONFINITE : 0u;
+}
+
+// Density (kernel summation), unlike-neighbour kernel sum S and Tait EOS of particle p,
+// walking its cell stencil.
+template <typename R, bool KAHAN>
+__device__ __forceinline__ uint32_t density_one(const DevState &s, const InstDesc *d, uint32_t p)
+{
+    const uint32_t N = s.N;
     const int cur = s.cur;
     const double *X = s.x[cur];
     const uint8_t *SK = s.sk[cur];
@@ -406,140 +440,570 @@ __global__ void k_density(DevState s)
     for_each_cell(s, d, cxyz & 1023, (cxyz >> 10) & 1023, cxyz >> 20, err,
                   [&](uint32_t b, uint32_t e) {
         for (uint32_t q = b; q < e; ++q) {
-            if (q == p) continue;
-            double dx0 = min_img(d, 0, xi0 - X[q]);
-            double dx1 = min_img(d, 1, xi1 - X[N + q]);
-            double dx2 = min_img(d, 2, xi2 - X[2 * N + q]);
-            double r2 = r2_exact(dx0, dx1, dx2);
-            if (r2 < cut2) {
+            const double xq0 = X[q], xq1 = X[N + q], xq2 = X[2 * N + q];
+            const int spq = SK[q] & 1;
+            double r2 = r2_exact(min_img(d, 0, xi0 - xq0), min_img(d, 1, xi1 - xq1),
+                                 min_img(d, 2, xi2 - xq2));
+            if (r2 < cut2 && q != p) {
                 R W = kernel_W<R>(kernel, (R)r2, inv_h, wnorm);
                 sw.add(W);
-                if ((SK[q] & 1) != spi) su.add(W);
+                su.add(spq != spi ? W : (R)0);
             }
         }
     });
-    double mi = d->mass[spi];
-    double rho, P;
-    if (kind == KIND_WALL_OUTER) {
-        rho = d->rho0;
-        P = 0.0;
-    } else {
-        rho = mi * (d->W0 + sw.value());
-        double r = rho / d->rho0;
-        double r2 = r * r;
-        P = d->B * ((r2 * r2) * (r2 * r) - 1.0);
-    }
-    double S = su.value();
-    double V = mi / rho;
-    double ir2 = 1.0 / (rho * rho);
-    R *aux = (R *)s.aux + 4 * (size_t)p;
-    aux[0] = (R)V;
-    aux[1] = (R)(P * ir2);
-    aux[2] = (R)ir2;
-    aux[3] = (R)(S > 0.0 ? V / S : 0.0);
-    R *rp = (R *)s.rhoP + 2 * (size_t)p;
-    rp[0] = (R)rho;
-    rp[1] = (R)P;
-    if (!isfinite(rho) || !isfinite(P)) err |= ERR_NONFINITE;
+    return err | density_finish<R>(s, d, p, spi, kind, sw.value(), su.value());
+}
+
+template <typename R, bool KAHAN>
+__global__ void k_density(DevState s)
+{
+    PIdx t = map_thread(s);
+    if (!t.active) return;
+    uint32_t err = density_one<R, KAHAN>(s, t.d, t.p);
     if (err) atomicOr(s.err, err);
 }
 
-// Pair forces and spin torques on fluid particles (walls: zero, their motion is imposed).
+// Coefficients of the pair force, in the pair precision.
+template <typename R>
+struct ForceK {
+    R m0, m1, sigT, eta4, Cl, inv_h, wnorm;
+    int kernel;
+    __device__ explicit ForceK(const InstDesc *d)
+        : m0((R)d->mass[0]), m1((R)d->mass[1]), sigT((R)d->sigma_T), eta4((R)(4.0 * d->eta)),
+          Cl((R)d->C_l), inv_h((R)d->inv_h), wnorm((R)d->wnorm), kernel(d->kernel) {}
+};
+
+// Per-particle inputs of the pair force: species, mass, V = m/rho, P/rho^2, 1/rho^2, V/S.
+template <typename R>
+struct ForceP {
+    int sp;
+    R m, V, Pr, ir2, VS;
+};
+
+// Force f on particle i from neighbour j and the spin torque n that both receive.
 //   pressure     m_i m_j (P_i/rho_i^2 + P_j/rho_j^2) F r
 //   interfacial  g_T (r_x, r_y, 0), g_T = -sigma_T m_i m_j (1/rho_i^2 + 1/rho_j^2) F, unlike
 //   viscous      -4 eta V_i V_j F (v_ij - (w_i + w_j)/2 × r), viscous-viscous pairs
 //   friction     -C_l W (V_i/S_i + V_j/S_j) v_ij, unlike pairs
-//   torque       -1/2 r × (non-central force), added to both particles of the pair
-template <typename R, bool KAHAN>
-__global__ void k_force(DevState s)
+//   torque       -1/2 r × (non-central force)
+// r = x_i - x_j (r2 its squared length), v = v_i - v_j, hs = (w_i + w_j)/2.
+template <typename R>
+__device__ __forceinline__ void pair_force(const ForceK<R> &k, const ForceP<R> &I, const ForceP<R> &J,
+                                           R r0, R r1, R r2, R rsq, R v0, R v1, R v2,
+                                           R hs0, R hs1, R hs2, R f[3], R n[3])
 {
-    PIdx t = map_thread(s);
-    if (!t.active) return;
-    const InstDesc *d = t.d;
-    const uint32_t p = t.p, N = s.N;
-    const int cur = s.cur;
+    R W, Fk;
+    kernel_WF<R>(k.kernel, rsq, k.inv_h, k.wnorm, W, Fk);
+    const R mm = I.m * J.m;
+    const R gp = mm * (I.Pr + J.Pr) * Fk;
+    R f0 = gp * r0, f1 = gp * r1, f2 = gp * r2;
+    R n0 = 0, n1 = 0;
+    R c0 = 0, c1 = 0, c2 = 0;  // non-central part
+    if (I.sp != J.sp) {
+        R gT = -k.sigT * mm * (I.ir2 + J.ir2) * Fk;
+        f0 += gT * r0;
+        f1 += gT * r1;
+        n0 = (R)0.5 * gT * r2 * r1;
+        n1 = (R)-0.5 * gT * r2 * r0;
+        R gm = -k.Cl * W * (I.VS + J.VS);
+        c0 = gm * v0; c1 = gm * v1; c2 = gm * v2;
+    }
+    if ((I.sp & J.sp) != 0) {
+        R u0 = v0 - (hs1 * r2 - hs2 * r1);
+        R u1 = v1 - (hs2 * r0 - hs0 * r2);
+        R u2 = v2 - (hs0 * r1 - hs1 * r0);
+        R gv = -k.eta4 * I.V * J.V * Fk;
+        c0 += gv * u0; c1 += gv * u1; c2 += gv * u2;
+    }
+    f[0] = f0 + c0; f[1] = f1 + c1; f[2] = f2 + c2;
+    n[0] = n0 + (R)-0.5 * (r1 * c2 - r2 * c1);
+    n[1] = n1 + (R)-0.5 * (r2 * c0 - r0 * c2);
+    n[2] = (R)-0.5 * (r0 * c1 - r1 * c0);
+}
+
+template <typename R>
+__device__ __forceinline__ uint32_t force_finish(const DevState &s, const InstDesc *d, uint32_t p,
+                                                 int spi, const double F[3], const double T[3])
+{
     R *acc = (R *)s.acc, *alpha = (R *)s.alpha;
+    const uint32_t N = s.N;
+    const double im = 1.0 / d->mass[spi], iI = 1.0 / d->inertia[spi];
+    uint32_t err = 0;
+    for (int a = 0; a < 3; a++) {
+        double av = F[a] * im, al = T[a] * iI;
+        acc[a * N + p] = (R)av;
+        alpha[a * N + p] = (R)al;
+        if (!isfinite(av) || !isfinite(al)) err |= ERR_NONFINITE;
+    }
+    return err;
+}
+
+template <typename R>
+__device__ __forceinline__ ForceP<R> force_particle_in(const DevState &s, const InstDesc *d,
+                                                       uint32_t q, int sp)
+{
+    const R *A = (const R *)s.aux + 4 * (size_t)q;
+    ForceP<R> P;
+    P.sp = sp;
+    P.m = (R)d->mass[sp];
+    P.V = A[0];
+    P.Pr = A[1];
+    P.ir2 = A[2];
+    P.VS = A[3];
+    return P;
+}
+
+// Pair forces and spin torques on particle p (walls get zero: their motion is imposed),
+// walking its cell stencil.
+template <typename R, bool KAHAN>
+__device__ __forceinline__ uint32_t force_one(const DevState &s, const InstDesc *d, uint32_t p)
+{
+    const uint32_t N = s.N;
+    const int cur = s.cur;
     const uint8_t *SK = s.sk[cur];
     const uint8_t ski = SK[p];
     if ((ski >> 1) != KIND_FLUID) {
-        for (int a = 0; a < 3; a++) { acc[a * N + p] = (R)0; alpha[a * N + p] = (R)0; }
-        return;
+        const double z[3] = {0.0, 0.0, 0.0};
+        return force_finish<R>(s, d, p, ski & 1, z, z);
     }
     const double *X = s.x[cur], *Vv = s.v[cur], *Ww = s.w[cur];
-    const R *AUX = (const R *)s.aux;
     const double xi0 = X[p], xi1 = X[N + p], xi2 = X[2 * N + p];
     const double vi0 = Vv[p], vi1 = Vv[N + p], vi2 = Vv[2 * N + p];
     const double wi0 = Ww[p], wi1 = Ww[N + p], wi2 = Ww[2 * N + p];
-    const int spi = ski & 1;
-    const R Vi = AUX[4 * (size_t)p], Pri = AUX[4 * (size_t)p + 1];
-    const R ir2i = AUX[4 * (size_t)p + 2], VSi = AUX[4 * (size_t)p + 3];
-    const R mi = (R)d->mass[spi];
-    const R m0 = (R)d->mass[0], m1 = (R)d->mass[1];
-    const R sigT = (R)d->sigma_T, eta4 = (R)(4.0 * d->eta), Cl = (R)d->C_l;
-    const int kernel = d->kernel;
+    const ForceK<R> K(d);
+    const ForceP<R> I = force_particle_in<R>(s, d, p, ski & 1);
     const double cut2 = d->cut2;
-    const R inv_h = (R)d->inv_h, wnorm = (R)d->wnorm;
     const uint32_t cxyz = s.cell_xyz[s.pcell[p]];
     uint32_t err = 0;
     Acc<R, KAHAN> F0, F1, F2, T0, T1, T2;
     for_each_cell(s, d, cxyz & 1023, (cxyz >> 10) & 1023, cxyz >> 20, err,
                   [&](uint32_t b, uint32_t e) {
         for (uint32_t q = b; q < e; ++q) {
-            if (q == p) continue;
-            double dx0 = min_img(d, 0, xi0 - X[q]);
-            double dx1 = min_img(d, 1, xi1 - X[N + q]);
-            double dx2 = min_img(d, 2, xi2 - X[2 * N + q]);
+            const double xq0 = X[q], xq1 = X[N + q], xq2 = X[2 * N + q];
+            double dx0 = min_img(d, 0, xi0 - xq0);
+            double dx1 = min_img(d, 1, xi1 - xq1);
+            double dx2 = min_img(d, 2, xi2 - xq2);
             double r2d = r2_exact(dx0, dx1, dx2);
-            if (!(r2d < cut2)) continue;
-            const int spj = SK[q] & 1;
-            const R Vj = AUX[4 * (size_t)q], Prj = AUX[4 * (size_t)q + 1];
-            const R ir2j = AUX[4 * (size_t)q + 2], VSj = AUX[4 * (size_t)q + 3];
-            const R mj = spj ? m1 : m0;
-            const R r0 = (R)dx0, r1 = (R)dx1, r2 = (R)dx2;
-            R W, Fk;
-            kernel_WF<R>(kernel, (R)r2d, inv_h, wnorm, W, Fk);
-            const R v0 = (R)(vi0 - Vv[q]), v1 = (R)(vi1 - Vv[N + q]), v2 = (R)(vi2 - Vv[2 * N + q]);
-            const R mm = mi * mj;
-            // pressure (central)
-            R gp = mm * (Pri + Prj) * Fk;
-            R f0 = gp * r0, f1 = gp * r1, f2 = gp * r2;
-            R n0 = 0, n1 = 0, n2 = 0;
-            R c0 = 0, c1 = 0, c2 = 0;  // non-central force
-            if (spj != spi) {
-                R gT = -sigT * mm * (ir2i + ir2j) * Fk;
-                f0 += gT * r0;
-                f1 += gT * r1;
-                n0 += (R)0.5 * gT * r2 * r1;
-                n1 += (R)-0.5 * gT * r2 * r0;
-                R gm = -Cl * W * (VSi + VSj);
-                c0 += gm * v0; c1 += gm * v1; c2 += gm * v2;
-            }
-            if ((spi & spj) != 0) {
-                const R s0 = (R)(0.5 * (wi0 + Ww[q])), s1 = (R)(0.5 * (wi1 + Ww[N + q])),
-                        s2 = (R)(0.5 * (wi2 + Ww[2 * N + q]));
-                R u0 = v0 - (s1 * r2 - s2 * r1);
-                R u1 = v1 - (s2 * r0 - s0 * r2);
-                R u2 = v2 - (s0 * r1 - s1 * r0);
-                R gv = -eta4 * Vi * Vj * Fk;
-                c0 += gv * u0; c1 += gv * u1; c2 += gv * u2;
-            }
-            f0 += c0; f1 += c1; f2 += c2;
-            n0 += (R)-0.5 * (r1 * c2 - r2 * c1);
-            n1 += (R)-0.5 * (r2 * c0 - r0 * c2);
-            n2 += (R)-0.5 * (r0 * c1 - r1 * c0);
-            F0.add(f0); F1.add(f1); F2.add(f2);
-            T0.add(n0); T1.add(n1); T2.add(n2);
+            if (!(r2d < cut2) || q == p) continue;
+            const ForceP<R> J = force_particle_in<R>(s, d, q, SK[q] & 1);
+            R f[3], n[3];
+            pair_force<R>(K, I, J, (R)dx0, (R)dx1, (R)dx2, (R)r2d,
+                          (R)(vi0 - Vv[q]), (R)(vi1 - Vv[N + q]), (R)(vi2 - Vv[2 * N + q]),
+                          (R)(0.5 * (wi0 + Ww[q])), (R)(0.5 * (wi1 + Ww[N + q])),
+                          (R)(0.5 * (wi2 + Ww[2 * N + q])), f, n);
+            F0.add(f[0]); F1.add(f[1]); F2.add(f[2]);
+            T0.add(n[0]); T1.add(n[1]); T2.add(n[2]);
         }
     });
-    double im = 1.0 / d->mass[spi];
-    double iI = 1.0 / d->inertia[spi];
-    double a0 = F0.value() * im, a1 = F1.value() * im, a2 = F2.value() * im;
-    double al0 = T0.value() * iI, al1 = T1.value() * iI, al2 = T2.value() * iI;
-    acc[p] = (R)a0; acc[N + p] = (R)a1; acc[2 * N + p] = (R)a2;
-    alpha[p] = (R)al0; alpha[N + p] = (R)al1; alpha[2 * N + p] = (R)al2;
-    if (!isfinite(a0) || !isfinite(a1) || !isfinite(a2) || !isfinite(al0) || !isfinite(al1) ||
-        !isfinite(al2))
-        err |= ERR_NONFINITE;
+    const double F[3] = {F0.value(), F1.value(), F2.value()};
+    const double T[3] = {T0.value(), T1.value(), T2.value()};
+    return err | force_finish<R>(s, d, p, ski & 1, F, T);
+}
+
+template <typename R, bool KAHAN>
+__global__ void k_force(DevState s)
+{
+    PIdx t = map_thread(s);
+    if (!t.active) return;
+    uint32_t err = force_one<R, KAHAN>(s, t.d, t.p);
+    if (err) atomicOr(s.err, err);
+}
+
+// ------------------------------------------------------------ brick sweeps ----------
+//
+// One workgroup per brick of 2x2x2 cells (edge >= 2h each).  The 4x4x4 cells around the
+// brick (its neighbourhood, periodic images shifted into the brick's frame) are staged in
+// LDS in slot order, x fastest, so the 27-cell stencil of a target cell is 9 contiguous
+// runs ("rows").  Wave w serves brick cell w: its lanes are (target, candidate group)
+// pairs, group g taking every G-th candidate of each row, so lanes of a group read the same
+// LDS word, and the G partial sums of a target are combined at the end in a fixed order.
+//
+// Each lane walks its trips in windows of at most 64: it first tests the window's
+// candidates into a 64-bit hit mask, then evaluates the pair terms of the set bits only, so
+// the pair arithmetic runs on compacted neighbours.  A per-wave table maps a bit back to
+// its candidate.  Positions are staged in single precision relative to the brick centre
+// (FP32-mixed path); neighbourhoods too large to stage fall back to the per-particle code.
+
+constexpr int kBrickThreads = 512;
+constexpr int kStageDensity = 2048;
+constexpr int kStageForce = 1408;
+
+struct BrickFrame {
+    uint32_t begin[64];   // sorted index of each slot's first particle
+    uint32_t off[65];     // staged index of each slot's first particle (prefix of counts)
+    double shift[64][3];  // periodic image shift of each slot
+    double origin[3];     // brick centre
+    uint32_t ok;          // 0: too many particles to stage (per-thread fallback)
+    int32_t win[kBrickThreads / 64][64];  // per wave: candidate = win[bit] + g + G * bit
+};
+
+// Fills the frame (threads 0..63) and returns the staged particle count.
+__device__ __forceinline__ uint32_t brick_frame(const DevState &s, const InstDesc *d, uint32_t bxyz,
+                                                BrickFrame &F, int stage_max)
+{
+    const int t = threadIdx.x;
+    const int b[3] = {(int)(bxyz & 1023), (int)((bxyz >> 10) & 1023), (int)(bxyz >> 20)};
+    if (t < 64) {
+        const int i[3] = {t & 3, (t >> 2) & 3, t >> 4};
+        int c[3];
+        bool valid = true;
+        for (int a = 0; a < 3; a++) {
+            c[a] = 2 * b[a] + i[a] - 1;
+            double sh = 0.0;
+            if (d->periodic[a]) {
+                if (c[a] < 0) { c[a] += d->n[a]; sh = -d->L[a]; }
+                else if (c[a] >= d->n[a]) { c[a] -= d->n[a]; sh = d->L[a]; }
+            } else if (c[a] < 0 || c[a] >= d->n[a]) {
+                valid = false;
+            }
+            F.shift[t][a] = sh;
+        }
+        uint32_t beg = 0, cnt = 0;
+        if (valid) {
+            uint32_t lin = (uint32_t)c[0] + (uint32_t)d->n[0] * ((uint32_t)c[1] + (uint32_t)d->n[1] * (uint32_t)c[2]);
+            uint32_t r = s.rank_of_lin[d->cell_off + lin];
+            beg = s.start[r];
+            cnt = s.start[r + 1] - beg;
+        }
+        F.begin[t] = beg;
+        F.off[t + 1] = cnt;  // counts; prefix taken below
+        if (t < 3) F.origin[t] = d->lo[t] + (double)(2 * b[t] + 1) * d->edge[t];
+    }
+    __syncthreads();
+    if (t == 0) {
+        uint32_t acc = 0;
+        bool ok = true;
+        F.off[0] = 0;
+        for (int k = 0; k < 64; k++) {
+            uint32_t c = F.off[k + 1];
+            if (c > (uint32_t)kMaxCell) ok = false;
+            acc += c;
+            F.off[k + 1] = acc;
+        }
+        F.ok = ok && acc <= (uint32_t)stage_max;
+    }
+    __syncthreads();
+    return F.off[64];
+}
+
+// Slot of staged particle k (largest slot whose first staged index is <= k).
+__device__ __forceinline__ int slot_of(const BrickFrame &F, uint32_t k)
+{
+    int lo = 0, hi = 63;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (F.off[mid] <= k) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// The brick cell served by wave w: its slot, and whether it lies in the grid.
+__device__ __forceinline__ bool brick_target(const InstDesc *d, uint32_t bxyz, int w, int ts[3])
+{
+    const int b[3] = {(int)(bxyz & 1023), (int)((bxyz >> 10) & 1023), (int)(bxyz >> 20)};
+    const int o[3] = {w & 1, (w >> 1) & 1, w >> 2};
+    bool in = true;
+    for (int a = 0; a < 3; a++) {
+        ts[a] = 1 + o[a];
+        if (2 * b[a] + o[a] >= d->n[a]) in = false;
+    }
+    return in;
+}
+
+__device__ __forceinline__ int slot_index(int x, int y, int z) { return x + 4 * (y + 4 * z); }
+
+// Sum of the G partial (Kahan) sums of a target, held by lanes t, t + ntc, ...
+__device__ __forceinline__ double group_total(float s_, float c_, int lane, int ntc, int G)
+{
+    double tot = 0.0;
+    for (int g = 0; g < G; g++) {
+        int src = lane + g * ntc;
+        float a = __shfl(s_, src < 64 ? src : lane);
+        float b = __shfl(c_, src < 64 ? src : lane);
+        tot += (double)a - (double)b;
+    }
+    return tot;
+}
+
+// Walks the stencil of the wave's target cell in windows of <= 64 trips.  test(k) decides
+// a hit on staged candidate k (only called for k inside its row); body(k) is then called
+// for every hit.  All lanes of the wave execute the same window and trip sequence.
+template <class Test, class Body>
+__device__ __forceinline__ void stencil_windows(const BrickFrame &F, int32_t *win, const int ts[3],
+                                                int lane, int g, int G, Test &&test, Body &&body)
+{
+    int r = 0;          // current row (dz * 3 + dy)
+    uint32_t done = 0;  // trips of row r already walked
+    while (r < 9) {
+        uint64_t mask = 0;
+        int W = 0;
+        while (r < 9 && W < 64) {
+            const int s0 = slot_index(ts[0] - 1, ts[1] - 1 + (r % 3), ts[2] - 1 + (r / 3));
+            const uint32_t b = F.off[s0], e = F.off[s0 + 3];
+            const uint32_t trips = (e - b + (uint32_t)G - 1) / (uint32_t)G;
+            const uint32_t take = min(trips - done, (uint32_t)(64 - W));
+            if (lane >= W && lane < W + (int)take)
+                win[lane] = (int32_t)(b + (uint32_t)G * done) - G * W;
+            for (uint32_t t = 0; t < take; t++) {
+                const uint32_t k = b + (uint32_t)g + (uint32_t)G * (done + t);
+                if (k < e && test(k)) mask |= 1ull << (W + (int)t);
+            }
+            W += (int)take;
+            done += take;
+            if (done == trips) { r++; done = 0; }
+        }
+        __builtin_amdgcn_wave_barrier();
+        while (mask) {
+            const int j = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            body((uint32_t)(win[j] + g + G * j));
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Single-precision W and F = -W'/r with the hardware square root and reciprocal.
+__device__ __forceinline__ void kernel_WF_fast(int kernel, float r2, float inv_h, float wnorm, float &W, float &F)
+{
+    const float q = fast_sqrt(r2) * inv_h;
+    const float ih2 = inv_h * inv_h;
+    if (kernel == KERNEL_WENDLAND) {
+        const float t = 1.0f - 0.5f * q;
+        const float t3 = t * t * t;
+        W = wnorm * t3 * t * (2.0f * q + 1.0f);
+        F = 5.0f * wnorm * t3 * ih2;
+    } else if (q < 1.0f) {
+        W = wnorm * (1.0f - 1.5f * q * q + 0.75f * q * q * q);
+        F = wnorm * (3.0f - 2.25f * q) * ih2;
+    } else {
+        const float t = 2.0f - q;
+        W = wnorm * 0.25f * t * t * t;
+        F = wnorm * 0.75f * t * t * ih2 * fast_rcp(q);
+    }
+}
+
+// The same pair terms as pair_force, without branches on the species: unlike and
+// viscous-viscous factors are 0/1 multipliers.
+__device__ __forceinline__ void pair_force_f32(const ForceK<float> &k, const ForceP<float> &I,
+                                               const ForceP<float> &J, float r0, float r1, float r2,
+                                               float v0, float v1, float v2, float hs0, float hs1,
+                                               float hs2, float f[3], float n[3])
+{
+    float W, Fk;
+    kernel_WF_fast(k.kernel, r0 * r0 + r1 * r1 + r2 * r2, k.inv_h, k.wnorm, W, Fk);
+    const float unl = I.sp != J.sp ? 1.0f : 0.0f;
+    const float nn = (I.sp & J.sp) ? 1.0f : 0.0f;
+    const float mm = I.m * J.m;
+    const float gp = mm * (I.Pr + J.Pr) * Fk;
+    const float gT = -k.sigT * mm * (I.ir2 + J.ir2) * Fk * unl;
+    const float gm = -k.Cl * W * (I.VS + J.VS) * unl;
+    const float gv = -k.eta4 * I.V * J.V * Fk * nn;
+    const float u0 = v0 - (hs1 * r2 - hs2 * r1);
+    const float u1 = v1 - (hs2 * r0 - hs0 * r2);
+    const float u2 = v2 - (hs0 * r1 - hs1 * r0);
+    const float c0 = gm * v0 + gv * u0, c1 = gm * v1 + gv * u1, c2 = gm * v2 + gv * u2;
+    const float gh = gp + gT;
+    f[0] = gh * r0 + c0;
+    f[1] = gh * r1 + c1;
+    f[2] = gp * r2 + c2;
+    const float hT = 0.5f * gT * r2;
+    n[0] = hT * r1 - 0.5f * (r1 * c2 - r2 * c1);
+    n[1] = -hT * r0 - 0.5f * (r2 * c0 - r0 * c2);
+    n[2] = -0.5f * (r0 * c1 - r1 * c0);
+}
+
+template <bool KAHAN>
+__global__ void __launch_bounds__(kBrickThreads) k_density_brick(DevState s)
+{
+    __shared__ BrickFrame F;
+    __shared__ float4 stage[kStageDensity];
+    const uint32_t bxyz = s.brick_xyz[blockIdx.x];
+    const InstDesc *d = s.desc + s.brick_inst[blockIdx.x];
+    const uint32_t N = s.N;
+    const int cur = s.cur;
+    const double *X = s.x[cur];
+    const uint8_t *SK = s.sk[cur];
+    const uint32_t M = brick_frame(s, d, bxyz, F, kStageDensity);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int ts[3];
+    const bool has_cell = brick_target(d, bxyz, w, ts);
+    const int tslot = slot_index(ts[0], ts[1], ts[2]);
+    uint32_t err = 0;
+    if (!F.ok) {
+        if (has_cell) {
+            const uint32_t nt = F.off[tslot + 1] - F.off[tslot];
+            for (uint32_t i = lane; i < nt; i += 64) err |= density_one<float, KAHAN>(s, d, F.begin[tslot] + i);
+        }
+        if (err) atomicOr(s.err, err);
+        return;
+    }
+    for (uint32_t k = threadIdx.x; k < M; k += kBrickThreads) {
+        const int sl = slot_of(F, k);
+        const uint32_t q = F.begin[sl] + (k - F.off[sl]);
+        float4 v;
+        v.x = (float)((X[q] + F.shift[sl][0]) - F.origin[0]);
+        v.y = (float)((X[N + q] + F.shift[sl][1]) - F.origin[1]);
+        v.z = (float)((X[2 * N + q] + F.shift[sl][2]) - F.origin[2]);
+        v.w = (float)(SK[q] & 1);
+        stage[k] = v;
+    }
+    __syncthreads();
+    if (!has_cell) return;
+    const uint32_t nt = F.off[tslot + 1] - F.off[tslot];
+    const float cut2 = (float)d->cut2, inv_h = (float)d->inv_h, wnorm = (float)d->wnorm;
+    const int kernel = d->kernel;
+    for (uint32_t chunk = 0; chunk < nt; chunk += 64) {
+        const int ntc = (int)min(64u, nt - chunk);
+        const int G = 64 / ntc;
+        const int g = lane / ntc, t = lane % ntc;
+        const bool active = g < G;
+        const uint32_t kself = F.off[tslot] + chunk + t;
+        const float4 me = stage[active ? kself : F.off[tslot]];
+        Acc<float, KAHAN> sw, su;
+        stencil_windows(F, F.win[w], ts, lane, active ? g : 0, G,
+            [&](uint32_t k) {
+                const float4 c = stage[k];
+                const float d0 = me.x - c.x, d1 = me.y - c.y, d2 = me.z - c.z;
+                return active && k != kself && d0 * d0 + d1 * d1 + d2 * d2 < cut2;
+            },
+            [&](uint32_t k) {
+                const float4 c = stage[k];
+                const float d0 = me.x - c.x, d1 = me.y - c.y, d2 = me.z - c.z;
+                const float q = fast_sqrt(d0 * d0 + d1 * d1 + d2 * d2) * inv_h;
+                float W;
+                if (kernel == KERNEL_WENDLAND) {
+                    const float tt = 1.0f - 0.5f * q;
+                    const float t2 = tt * tt;
+                    W = wnorm * t2 * t2 * (2.0f * q + 1.0f);
+                } else if (q < 1.0f) {
+                    W = wnorm * (1.0f - 1.5f * q * q + 0.75f * q * q * q);
+                } else {
+                    const float tt = 2.0f - q;
+                    W = wnorm * 0.25f * tt * tt * tt;
+                }
+                sw.add(W);
+                su.add(c.w != me.w ? W : 0.0f);
+            });
+        const double SW = group_total(sw.s, KAHAN ? sw.c : 0.0f, lane, ntc, G);
+        const double SU = group_total(su.s, KAHAN ? su.c : 0.0f, lane, ntc, G);
+        if (active && g == 0) {
+            const uint32_t p = F.begin[tslot] + chunk + t;
+            const uint8_t ski = SK[p];
+            err |= density_finish<float>(s, d, p, ski & 1, ski >> 1, SW, SU);
+        }
+    }
+    if (err) atomicOr(s.err, err);
+}
+
+template <bool KAHAN>
+__global__ void __launch_bounds__(kBrickThreads) k_force_brick(DevState s)
+{
+    __shared__ BrickFrame F;
+    __shared__ float4 SA[kStageForce];   // position (brick frame), P/rho^2
+    __shared__ float4 SB[kStageForce];   // velocity - v_ref, V (negative: viscous species)
+    __shared__ float4 SC[kStageForce];   // spin, V/S
+    __shared__ double vref[3];
+    const uint32_t bxyz = s.brick_xyz[blockIdx.x];
+    const InstDesc *d = s.desc + s.brick_inst[blockIdx.x];
+    const uint32_t N = s.N;
+    const int cur = s.cur;
+    const double *X = s.x[cur], *Vv = s.v[cur], *Ww = s.w[cur];
+    const uint8_t *SK = s.sk[cur];
+    const float *AUX = (const float *)s.aux;
+    const uint32_t M = brick_frame(s, d, bxyz, F, kStageForce);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int ts[3];
+    const bool has_cell = brick_target(d, bxyz, w, ts);
+    const int tslot = slot_index(ts[0], ts[1], ts[2]);
+    uint32_t err = 0;
+    if (!F.ok) {
+        if (has_cell) {
+            const uint32_t nt = F.off[tslot + 1] - F.off[tslot];
+            for (uint32_t i = lane; i < nt; i += 64) err |= force_one<float, KAHAN>(s, d, F.begin[tslot] + i);
+        }
+        if (err) atomicOr(s.err, err);
+        return;
+    }
+    if (threadIdx.x < 3) {
+        const int c0 = slot_index(1, 1, 1);
+        vref[threadIdx.x] = F.off[c0 + 1] > F.off[c0] ? Vv[threadIdx.x * N + F.begin[c0]] : 0.0;
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < M; k += kBrickThreads) {
+        const int sl = slot_of(F, k);
+        const uint32_t q = F.begin[sl] + (k - F.off[sl]);
+        const float4 aq = *(const float4 *)(AUX + 4 * (size_t)q);
+        const int sp = SK[q] & 1;
+        SA[k] = make_float4((float)((X[q] + F.shift[sl][0]) - F.origin[0]),
+                            (float)((X[N + q] + F.shift[sl][1]) - F.origin[1]),
+                            (float)((X[2 * N + q] + F.shift[sl][2]) - F.origin[2]), aq.y);
+        SB[k] = make_float4((float)(Vv[q] - vref[0]), (float)(Vv[N + q] - vref[1]),
+                            (float)(Vv[2 * N + q] - vref[2]), sp ? -aq.x : aq.x);
+        SC[k] = make_float4((float)Ww[q], (float)Ww[N + q], (float)Ww[2 * N + q], aq.w);
+    }
+    __syncthreads();
+    if (!has_cell) return;
+    const uint32_t nt = F.off[tslot + 1] - F.off[tslot];
+    const float cut2 = (float)d->cut2;
+    const ForceK<float> K(d);
+    const float im2_0 = (float)(1.0 / (d->mass[0] * d->mass[0]));
+    const float im2_1 = (float)(1.0 / (d->mass[1] * d->mass[1]));
+    for (uint32_t chunk = 0; chunk < nt; chunk += 64) {
+        const int ntc = (int)min(64u, nt - chunk);
+        const int G = 64 / ntc;
+        const int g = lane / ntc, t = lane % ntc;
+        const bool target = g < G;
+        const uint32_t kself = F.off[tslot] + chunk + t;
+        const uint32_t p = F.begin[tslot] + chunk + t;
+        const bool fluid = target && (SK[p] >> 1) == KIND_FLUID;
+        const uint32_t ki = target ? kself : F.off[tslot];
+        const float4 Ai = SA[ki], Bi = SB[ki], Ci = SC[ki];
+        ForceP<float> I;
+        I.sp = Bi.w < 0.0f ? 1 : 0;
+        I.m = I.sp ? K.m1 : K.m0;
+        I.V = fabsf(Bi.w);
+        I.Pr = Ai.w;
+        I.ir2 = I.V * I.V * (I.sp ? im2_1 : im2_0);
+        I.VS = Ci.w;
+        Acc<float, KAHAN> F0, F1, F2, T0, T1, T2;
+        stencil_windows(F, F.win[w], ts, lane, target ? g : 0, G,
+            [&](uint32_t k) {
+                const float4 c = SA[k];
+                const float d0 = Ai.x - c.x, d1 = Ai.y - c.y, d2 = Ai.z - c.z;
+                return fluid && k != kself && d0 * d0 + d1 * d1 + d2 * d2 < cut2;
+            },
+            [&](uint32_t k) {
+                const float4 A = SA[k], B = SB[k], C = SC[k];
+                ForceP<float> J;
+                J.sp = B.w < 0.0f ? 1 : 0;
+                J.m = J.sp ? K.m1 : K.m0;
+                J.V = fabsf(B.w);
+                J.Pr = A.w;
+                J.ir2 = J.V * J.V * (J.sp ? im2_1 : im2_0);
+                J.VS = C.w;
+                float f[3], n[3];
+                pair_force_f32(K, I, J, Ai.x - A.x, Ai.y - A.y, Ai.z - A.z, Bi.x - B.x,
+                               Bi.y - B.y, Bi.z - B.z, 0.5f * (Ci.x + C.x), 0.5f * (Ci.y + C.y),
+                               0.5f * (Ci.z + C.z), f, n);
+                F0.add(f[0]); F1.add(f[1]); F2.add(f[2]);
+                T0.add(n[0]); T1.add(n[1]); T2.add(n[2]);
+            });
+        const double f0 = group_total(F0.s, KAHAN ? F0.c : 0.0f, lane, ntc, G);
+        const double f1 = group_total(F1.s, KAHAN ? F1.c : 0.0f, lane, ntc, G);
+        const double f2 = group_total(F2.s, KAHAN ? F2.c : 0.0f, lane, ntc, G);
+        const double t0 = group_total(T0.s, KAHAN ? T0.c : 0.0f, lane, ntc, G);
+        const double t1 = group_total(T1.s, KAHAN ? T1.c : 0.0f, lane, ntc, G);
+        const double t2 = group_total(T2.s, KAHAN ? T2.c : 0.0f, lane, ntc, G);
+        if (target && g == 0) {
+            const double FF[3] = {fluid ? f0 : 0.0, fluid ? f1 : 0.0, fluid ? f2 : 0.0};
+            const double TT[3] = {fluid ? t0 : 0.0, fluid ? t1 : 0.0, fluid ? t2 : 0.0};
+            err |= force_finish<float>(s, d, p, I.sp, FF, TT);
+        }
+    }
     if (err) atomicOr(s.err, err);
 }
 
@@ -784,6 +1248,7 @@ hipError_t launch_density(const DevState &d, const Launch &L, hipStream_t st)
 {
     unsigned g = grid_for(d.n_waves, L.bs_density);
     if (d.precision == 0) k_density<double, false><<<g, L.bs_density, 0, st>>>(d);
+    else if (L.sweep == SWEEP_BRICK && d.n_bricks) k_density_brick<true><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
     else k_density<float, true><<<g, L.bs_density, 0, st>>>(d);
     return hipGetLastError();
 }
@@ -792,6 +1257,7 @@ hipError_t launch_force(const DevState &d, const Launch &L, hipStream_t st)
 {
     unsigned g = grid_for(d.n_waves, L.bs_force);
     if (d.precision == 0) k_force<double, false><<<g, L.bs_force, 0, st>>>(d);
+    else if (L.sweep == SWEEP_BRICK && d.n_bricks) k_force_brick<true><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
     else k_force<float, true><<<g, L.bs_force, 0, st>>>(d);
     return hipGetLastError();
 }

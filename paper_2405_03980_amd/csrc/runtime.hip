@@ -143,7 +143,7 @@ struct Carver {
     }
 };
 
-void carve(Carver &c, DevState &d, int n_inst, uint32_t N, uint32_t C, int precision)
+void carve(Carver &c, DevState &d, int n_inst, uint32_t N, uint32_t C, uint32_t NB, int precision)
 {
     size_t rs = precision == SPH_FP64 ? sizeof(double) : sizeof(float);
     size_t n3 = 3 * (size_t)N;
@@ -172,11 +172,15 @@ void carve(Carver &c, DevState &d, int n_inst, uint32_t N, uint32_t C, int preci
     d.err = c.take<uint32_t>(4);
     d.diag_part = c.take<double>((size_t)n_inst * kDiagChunks * 14);
     d.diag_out = c.take<double>((size_t)n_inst * 7);
+    d.brick_xyz = c.take<uint32_t>(NB ? NB : 1);
+    d.brick_inst = c.take<uint32_t>(NB ? NB : 1);
+    d.n_bricks = NB;
 }
 
 struct Plan {
     std::vector<InstDesc> desc;
     uint32_t N = 0, C = 0, n_waves = 0;
+    uint32_t n_bricks = 0;  // 0 unless every instance has cell_factor 1
 };
 
 sph_status plan(int32_t n_inst, const sph_params *params, const int64_t *counts, Plan &pl,
@@ -200,7 +204,8 @@ sph_status plan(int32_t n_inst, const sph_params *params, const int64_t *counts,
             d.lo[a] = p->lo[a];
             d.hi[a] = p->hi[a];
             d.L[a] = p->hi[a] - p->lo[a];
-            d.halfL[a] = 0.5 * d.L[a];
+            // bounded axes: an infinite half period disables the minimum image
+            d.halfL[a] = is_periodic(p->geometry, a) ? 0.5 * d.L[a] : INFINITY;
             d.edge[a] = edge[a];
             d.n[a] = n[a];
             d.periodic[a] = is_periodic(p->geometry, a) ? 1 : 0;
@@ -238,6 +243,13 @@ sph_status plan(int32_t n_inst, const sph_params *params, const int64_t *counts,
     pl.N = (uint32_t)N;
     pl.C = (uint32_t)C;
     pl.n_waves = (uint32_t)W;
+    uint64_t NB = 0;
+    bool bricks = true;
+    for (const InstDesc &d : pl.desc) {
+        if (d.cf != 1) bricks = false;
+        NB += (uint64_t)((d.n[0] + 1) / 2) * ((d.n[1] + 1) / 2) * ((d.n[2] + 1) / 2);
+    }
+    pl.n_bricks = bricks ? (uint32_t)NB : 0u;
     return SPH_OK;
 }
 
@@ -263,6 +275,29 @@ void cell_tables(const Plan &pl, std::vector<uint32_t> &rank_of_lin, std::vector
             uint32_t z = lin / ((uint32_t)d.n[0] * (uint32_t)d.n[1]);
             rank_of_lin[d.cell_off + lin] = d.cell_off + r;
             xyz[d.cell_off + r] = x | (y << 10) | (z << 20);
+        }
+    }
+}
+
+// Bricks of 2x2x2 cells, Morton order within each instance.
+void brick_tables(const Plan &pl, std::vector<uint32_t> &xyz, std::vector<uint32_t> &inst)
+{
+    xyz.clear();
+    inst.clear();
+    if (!pl.n_bricks) return;
+    std::vector<uint64_t> keys;
+    for (size_t i = 0; i < pl.desc.size(); i++) {
+        const InstDesc &d = pl.desc[i];
+        const uint32_t nb[3] = {(uint32_t)(d.n[0] + 1) / 2, (uint32_t)(d.n[1] + 1) / 2, (uint32_t)(d.n[2] + 1) / 2};
+        keys.clear();
+        for (uint32_t z = 0; z < nb[2]; z++)
+            for (uint32_t y = 0; y < nb[1]; y++)
+                for (uint32_t x = 0; x < nb[0]; x++)
+                    keys.push_back(((uint64_t)morton3_host(x, y, z) << 32) | (x | (y << 10) | (z << 20)));
+        std::sort(keys.begin(), keys.end());
+        for (uint64_t k : keys) {
+            xyz.push_back((uint32_t)(k & 0xffffffffu));
+            inst.push_back((uint32_t)i);
         }
     }
 }
@@ -540,7 +575,7 @@ sph_status sph_batch_workspace_bytes(int32_t n_inst, const sph_params *params,
     if (st != SPH_OK) return st;
     Carver c;
     DevState d{};
-    carve(c, d, n_inst, pl.N, pl.C, params[0].precision);
+    carve(c, d, n_inst, pl.N, pl.C, pl.n_bricks, params[0].precision);
     *bytes = c.off;
     return SPH_OK;
 }
@@ -560,7 +595,7 @@ sph_status sph_batch_create(int32_t n_inst, const sph_params *params, const int6
     if (st != SPH_OK) return st;
     Carver c;
     DevState d{};
-    carve(c, d, n_inst, pl.N, pl.C, params[0].precision);
+    carve(c, d, n_inst, pl.N, pl.C, pl.n_bricks, params[0].precision);
     if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || ws_bytes < c.off) return SPH_E_WORKSPACE;
     sph_batch *b = new (std::nothrow) sph_batch();
     if (!b) return SPH_E_INVALID;
@@ -570,20 +605,23 @@ sph_status sph_batch_create(int32_t n_inst, const sph_params *params, const int6
     b->steptab.assign(n_inst, StepParams{1.0, 0.0, 0.0, 0.0});
     Carver c2;
     c2.base = (char *)workspace;
-    carve(c2, b->ds, n_inst, pl.N, pl.C, params[0].precision);
+    carve(c2, b->ds, n_inst, pl.N, pl.C, pl.n_bricks, params[0].precision);
     b->ds.precision = params[0].precision;
     b->ds.n_inst = n_inst;
     b->ds.cur = 0;
     b->ds.N = pl.N;
     b->ds.C = pl.C;
     b->ds.n_waves = pl.n_waves;
-    std::vector<uint32_t> rank_of_lin, xyz;
+    std::vector<uint32_t> rank_of_lin, xyz, bxyz, binst;
     cell_tables(pl, rank_of_lin, xyz);
+    brick_tables(pl, bxyz, binst);
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMemcpyAsync(b->ds.desc, pl.desc.data(), sizeof(InstDesc) * n_inst, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->ds.steptab, b->steptab.data(), sizeof(StepParams) * n_inst, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->ds.rank_of_lin, rank_of_lin.data(), sizeof(uint32_t) * pl.C, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->ds.cell_xyz, xyz.data(), sizeof(uint32_t) * pl.C, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && pl.n_bricks) e = hipMemcpyAsync(b->ds.brick_xyz, bxyz.data(), sizeof(uint32_t) * pl.n_bricks, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && pl.n_bricks) e = hipMemcpyAsync(b->ds.brick_inst, binst.data(), sizeof(uint32_t) * pl.n_bricks, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = launch_fill_u32(b->ds.count, 0u, pl.C, b->stream);
     if (e == hipSuccess) e = launch_fill_u32(b->ds.start + pl.C, pl.N, 1, b->stream);
     if (e == hipSuccess) e = launch_fill_u32(b->ds.err, 0u, 4, b->stream);
@@ -652,6 +690,8 @@ sph_status sph_batch_set_tuning(sph_batch *b, const sph_tuning *t)
             return SPH_E_INVALID;
         }
     if (t->use_graph < -1 || t->use_graph > 1) { b->err = "use_graph must be -1, 0 or 1"; return SPH_E_INVALID; }
+    if (t->sweep < 0 || t->sweep > 2) { b->err = "sweep must be 0, 1 or 2"; return SPH_E_INVALID; }
+    if (t->sweep) b->L.sweep = t->sweep;
     if (t->block_density) b->L.bs_density = t->block_density;
     if (t->block_force) b->L.bs_force = t->block_force;
     if (t->block_stream) b->L.bs_stream = t->block_stream;
@@ -802,6 +842,7 @@ sph_status sph_get_tuning(const sph_sim *s, sph_tuning *t)
     t->block_force = s->b->L.bs_force;
     t->block_stream = s->b->L.bs_stream;
     t->use_graph = s->b->use_graph ? 1 : 0;
+    t->sweep = s->b->L.sweep;
     return SPH_OK;
 }
 

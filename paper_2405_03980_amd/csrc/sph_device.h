@@ -63,10 +63,19 @@ struct DevState {
     uint32_t *err;
     double *diag_part;            // [n_inst][kDiagChunks][14]
     double *diag_out;             // [n_inst][7]
+    // Bricks of 2x2x2 cells (instances with one cell per interaction radius):
+    // packed (bx | by << 10 | bz << 20) and instance index, in Morton order per instance.
+    uint32_t *brick_xyz, *brick_inst;
+    uint32_t n_bricks;
 };
+
+// Sweep implementations: one thread per particle walking its own cell stencil, or one
+// workgroup per 2x2x2-cell brick with the brick's neighbourhood staged in LDS.
+enum { SWEEP_THREAD = 1, SWEEP_BRICK = 2 };
 
 struct Launch {
     int bs_density = 256, bs_force = 256, bs_stream = 256;
+    int sweep = SWEEP_BRICK;  // used when every instance allows it (FP32-mixed, cf = 1)
 };
 
 // Launchers (kernels.hip).  All enqueue on `st` and return hipGetLastError().

@@ -151,8 +151,8 @@ class Simulation:
         _check(st, "sph_debug_neighbors", self._err)
         return row.cpu().numpy(), cols[: nnz.value].cpu().numpy()
 
-    def set_tuning(self, block_density=0, block_force=0, block_stream=0, use_graph=-1):
-        t = L.SphTuning(block_density, block_force, block_stream, use_graph)
+    def set_tuning(self, block_density=0, block_force=0, block_stream=0, use_graph=-1, sweep=0):
+        t = L.SphTuning(block_density, block_force, block_stream, use_graph, sweep)
         _check(self.lib.sph_set_tuning(self._h, C.byref(t)), "sph_set_tuning", self._err)
 
     def profile_begin(self):
@@ -169,7 +169,7 @@ class Simulation:
         t = L.SphTuning()
         _check(self.lib.sph_get_tuning(self._h, C.byref(t)), "sph_get_tuning", self._err)
         return dict(block_density=t.block_density, block_force=t.block_force,
-                    block_stream=t.block_stream, use_graph=t.use_graph)
+                    block_stream=t.block_stream, use_graph=t.use_graph, sweep=t.sweep)
 
 
 class Batch:
@@ -256,8 +256,8 @@ class Batch:
         _check(self.lib.sph_batch_diagnostics(self._h, out), "sph_batch_diagnostics", self._err)
         return np.array(out[:]).reshape(self.n_inst, 7)
 
-    def set_tuning(self, block_density=0, block_force=0, block_stream=0, use_graph=-1):
-        t = L.SphTuning(block_density, block_force, block_stream, use_graph)
+    def set_tuning(self, block_density=0, block_force=0, block_stream=0, use_graph=-1, sweep=0):
+        t = L.SphTuning(block_density, block_force, block_stream, use_graph, sweep)
         _check(self.lib.sph_batch_set_tuning(self._h, C.byref(t)), "sph_batch_set_tuning", self._err)
 
     def profile_begin(self):
