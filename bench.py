@@ -55,7 +55,23 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2405_03980_amd", "tuned.json"))
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
+                    help="only run a plain device-to-device copy of this size (5 times), to "
+                         "calibrate the HBM traffic counters, and exit")
     return ap.parse_args()
+
+
+def copy_calibration(mib: int) -> None:
+    """Plain copy kernel of known size: FETCH_SIZE and WRITE_SIZE of these dispatches
+    should each read `mib` MiB; their ratio to that is the counters' scale factor."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_MiB": mib, "bytes_per_copy": 4 * n}), flush=True)
 
 
 def load_tuning(path, name):
@@ -90,6 +106,9 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU slab "
               "decomposition is a design, not a build", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     import torch
     from paper_2405_03980_amd import _lib as L
     from paper_2405_03980_amd import inputs as I

@@ -726,17 +726,36 @@ __device__ __forceinline__ double group_total(float s_, float c_, int lane, int 
     return tot;
 }
 
-// Walks the stencil of the wave's target cell in windows of <= 64 trips.  test(k) decides
-// a hit on staged candidate k (only called for k inside its row); body(k) is then called
-// for every hit.  All lanes of the wave execute the same window and trip sequence.
-template <class Test, class Body>
+// Trips of the stencil walk of the wave's target cell (rows split over G groups) and
+// whether the masks of all its windows fit the per-particle mask slots.
+__device__ __forceinline__ bool masks_fit(const BrickFrame &F, const int ts[3], int G)
+{
+    uint32_t T = 0;
+    for (int r = 0; r < 9; r++) {
+        const int s0 = slot_index(ts[0] - 1, ts[1] - 1 + (r % 3), ts[2] - 1 + (r / 3));
+        T += (F.off[s0 + 3] - F.off[s0] + (uint32_t)G - 1) / (uint32_t)G;
+    }
+    return (uint32_t)G * ((T + 63) / 64) <= (uint32_t)kMaskSlots;
+}
+
+// Walks the stencil of the wave's target cell in windows of <= 64 trips.  Per window each
+// lane builds a 64-bit hit mask, bit t = trip t, either by test(k, in_row) (when in_row is
+// false, the group's last trip ran past its row, k is clamped into the row and the test
+// must return false) or, when `replay`, by loading the mask recorded by an earlier walk
+// from rec[window * G].  When `record`, the mask is stored to rec[window * G].  body(k) is
+// then called for every hit, two at a time (body2) so that their LDS loads overlap.  All
+// lanes of the wave execute the same window and trip sequence.
+template <class Test, class Body, class Body2>
 __device__ __forceinline__ void stencil_windows(const BrickFrame &F, int32_t *win, const int ts[3],
-                                                int lane, int g, int G, Test &&test, Body &&body)
+                                                int lane, int g, int G, bool record, bool replay,
+                                                uint64_t *rec, Test &&test, Body &&body,
+                                                Body2 &&body2)
 {
     int r = 0;          // current row (dz * 3 + dy)
     uint32_t done = 0;  // trips of row r already walked
+    int wi = 0;         // window index
     while (r < 9) {
-        uint64_t mask = 0;
+        uint32_t mlo = 0, mhi = 0;
         int W = 0;
         while (r < 9 && W < 64) {
             const int s0 = slot_index(ts[0] - 1, ts[1] - 1 + (r % 3), ts[2] - 1 + (r / 3));
@@ -745,19 +764,41 @@ __device__ __forceinline__ void stencil_windows(const BrickFrame &F, int32_t *wi
             const uint32_t take = min(trips - done, (uint32_t)(64 - W));
             if (lane >= W && lane < W + (int)take)
                 win[lane] = (int32_t)(b + (uint32_t)G * done) - G * W;
-            for (uint32_t t = 0; t < take; t++) {
-                const uint32_t k = b + (uint32_t)g + (uint32_t)G * (done + t);
-                if (k < e && test(k)) mask |= 1ull << (W + (int)t);
+            if (!replay) {
+                const uint32_t kb = b + (uint32_t)g + (uint32_t)G * done;
+#pragma unroll 4
+                for (uint32_t t = 0; t < take; t++) {
+                    const uint32_t k = kb + (uint32_t)G * t;
+                    const bool in_row = k < e;
+                    const uint32_t bit = (uint32_t)test(in_row ? k : e - 1, in_row);
+                    const int pos = W + (int)t;
+                    if (pos < 32) mlo |= bit << pos;
+                    else mhi |= bit << (pos - 32);
+                }
             }
             W += (int)take;
             done += take;
             if (done == trips) { r++; done = 0; }
         }
+        uint64_t mask;
+        if (replay) {
+            mask = rec ? rec[wi * G] : 0ull;
+        } else {
+            mask = ((uint64_t)mhi << 32) | mlo;
+            if (record && rec) rec[wi * G] = mask;
+        }
+        wi++;
         __builtin_amdgcn_wave_barrier();
         while (mask) {
-            const int j = __builtin_ctzll(mask);
+            const int j0 = __builtin_ctzll(mask);
             mask &= mask - 1;
-            body((uint32_t)(win[j] + g + G * j));
+            if (mask) {
+                const int j1 = __builtin_ctzll(mask);
+                mask &= mask - 1;
+                body2((uint32_t)(win[j0] + g + G * j0), (uint32_t)(win[j1] + g + G * j1));
+            } else {
+                body((uint32_t)(win[j0] + g + G * j0));
+            }
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -864,29 +905,39 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_brick(DevState s)
         const uint32_t kself = F.off[tslot] + chunk + t;
         const float4 me = stage[active ? kself : F.off[tslot]];
         Acc<float, KAHAN> sw, su;
-        stencil_windows(F, F.win[w], ts, lane, active ? g : 0, G,
-            [&](uint32_t k) {
+        auto wval = [&](const float4 &c) {
+            const float d0 = me.x - c.x, d1 = me.y - c.y, d2 = me.z - c.z;
+            const float q = fast_sqrt(d0 * d0 + d1 * d1 + d2 * d2) * inv_h;
+            if (kernel == KERNEL_WENDLAND) {
+                const float tt = 1.0f - 0.5f * q;
+                const float t2 = tt * tt;
+                return wnorm * t2 * t2 * (2.0f * q + 1.0f);
+            }
+            if (q < 1.0f) return wnorm * (1.0f - 1.5f * q * q + 0.75f * q * q * q);
+            const float tt = 2.0f - q;
+            return wnorm * 0.25f * tt * tt * tt;
+        };
+        const bool rec_ok = masks_fit(F, ts, G);
+        uint64_t *rec = (rec_ok && active) ? s.masks + (size_t)(F.begin[tslot] + chunk + t) * kMaskSlots + g : nullptr;
+        stencil_windows(F, F.win[w], ts, lane, active ? g : 0, G, rec_ok, false, rec,
+            [&](uint32_t k, bool in_row) {
                 const float4 c = stage[k];
                 const float d0 = me.x - c.x, d1 = me.y - c.y, d2 = me.z - c.z;
-                return active && k != kself && d0 * d0 + d1 * d1 + d2 * d2 < cut2;
+                return in_row & active & (k != kself) & (d0 * d0 + d1 * d1 + d2 * d2 < cut2);
             },
             [&](uint32_t k) {
                 const float4 c = stage[k];
-                const float d0 = me.x - c.x, d1 = me.y - c.y, d2 = me.z - c.z;
-                const float q = fast_sqrt(d0 * d0 + d1 * d1 + d2 * d2) * inv_h;
-                float W;
-                if (kernel == KERNEL_WENDLAND) {
-                    const float tt = 1.0f - 0.5f * q;
-                    const float t2 = tt * tt;
-                    W = wnorm * t2 * t2 * (2.0f * q + 1.0f);
-                } else if (q < 1.0f) {
-                    W = wnorm * (1.0f - 1.5f * q * q + 0.75f * q * q * q);
-                } else {
-                    const float tt = 2.0f - q;
-                    W = wnorm * 0.25f * tt * tt * tt;
-                }
+                const float W = wval(c);
                 sw.add(W);
                 su.add(c.w != me.w ? W : 0.0f);
+            },
+            [&](uint32_t k0, uint32_t k1) {
+                const float4 c0 = stage[k0], c1 = stage[k1];
+                const float W0 = wval(c0), W1 = wval(c1);
+                sw.add(W0);
+                su.add(c0.w != me.w ? W0 : 0.0f);
+                sw.add(W1);
+                su.add(c1.w != me.w ? W1 : 0.0f);
             });
         const double SW = group_total(sw.s, KAHAN ? sw.c : 0.0f, lane, ntc, G);
         const double SU = group_total(su.s, KAHAN ? su.c : 0.0f, lane, ntc, G);
@@ -970,27 +1021,44 @@ __global__ void __launch_bounds__(kBrickThreads) k_force_brick(DevState s)
         I.ir2 = I.V * I.V * (I.sp ? im2_1 : im2_0);
         I.VS = Ci.w;
         Acc<float, KAHAN> F0, F1, F2, T0, T1, T2;
-        stencil_windows(F, F.win[w], ts, lane, target ? g : 0, G,
-            [&](uint32_t k) {
+        auto pair = [&](const float4 &A, const float4 &B, const float4 &C, float f[3], float n[3]) {
+            ForceP<float> J;
+            J.sp = B.w < 0.0f ? 1 : 0;
+            J.m = J.sp ? K.m1 : K.m0;
+            J.V = fabsf(B.w);
+            J.Pr = A.w;
+            J.ir2 = J.V * J.V * (J.sp ? im2_1 : im2_0);
+            J.VS = C.w;
+            pair_force_f32(K, I, J, Ai.x - A.x, Ai.y - A.y, Ai.z - A.z, Bi.x - B.x, Bi.y - B.y,
+                           Bi.z - B.z, 0.5f * (Ci.x + C.x), 0.5f * (Ci.y + C.y),
+                           0.5f * (Ci.z + C.z), f, n);
+        };
+        auto accum = [&](const float f[3], const float n[3]) {
+            F0.add(f[0]); F1.add(f[1]); F2.add(f[2]);
+            T0.add(n[0]); T1.add(n[1]); T2.add(n[2]);
+        };
+        const bool replay = masks_fit(F, ts, G);
+        const uint64_t *recp = (replay && fluid) ? s.masks + (size_t)p * kMaskSlots + g : nullptr;
+        stencil_windows(F, F.win[w], ts, lane, target ? g : 0, G, false, replay,
+                        const_cast<uint64_t *>(recp),
+            [&](uint32_t k, bool in_row) {
                 const float4 c = SA[k];
                 const float d0 = Ai.x - c.x, d1 = Ai.y - c.y, d2 = Ai.z - c.z;
-                return fluid && k != kself && d0 * d0 + d1 * d1 + d2 * d2 < cut2;
+                return in_row & fluid & (k != kself) & (d0 * d0 + d1 * d1 + d2 * d2 < cut2);
             },
             [&](uint32_t k) {
-                const float4 A = SA[k], B = SB[k], C = SC[k];
-                ForceP<float> J;
-                J.sp = B.w < 0.0f ? 1 : 0;
-                J.m = J.sp ? K.m1 : K.m0;
-                J.V = fabsf(B.w);
-                J.Pr = A.w;
-                J.ir2 = J.V * J.V * (J.sp ? im2_1 : im2_0);
-                J.VS = C.w;
                 float f[3], n[3];
-                pair_force_f32(K, I, J, Ai.x - A.x, Ai.y - A.y, Ai.z - A.z, Bi.x - B.x,
-                               Bi.y - B.y, Bi.z - B.z, 0.5f * (Ci.x + C.x), 0.5f * (Ci.y + C.y),
-                               0.5f * (Ci.z + C.z), f, n);
-                F0.add(f[0]); F1.add(f[1]); F2.add(f[2]);
-                T0.add(n[0]); T1.add(n[1]); T2.add(n[2]);
+                pair(SA[k], SB[k], SC[k], f, n);
+                accum(f, n);
+            },
+            [&](uint32_t k0, uint32_t k1) {
+                const float4 A0 = SA[k0], B0 = SB[k0], C0 = SC[k0];
+                const float4 A1 = SA[k1], B1 = SB[k1], C1 = SC[k1];
+                float f0[3], n0[3], f1[3], n1[3];
+                pair(A0, B0, C0, f0, n0);
+                pair(A1, B1, C1, f1, n1);
+                accum(f0, n0);
+                accum(f1, n1);
             });
         const double f0 = group_total(F0.s, KAHAN ? F0.c : 0.0f, lane, ntc, G);
         const double f1 = group_total(F1.s, KAHAN ? F1.c : 0.0f, lane, ntc, G);

@@ -67,7 +67,12 @@ struct DevState {
     // packed (bx | by << 10 | bz << 20) and instance index, in Morton order per instance.
     uint32_t *brick_xyz, *brick_inst;
     uint32_t n_bricks;
+    // Neighbour hit masks of the brick sweeps, kMaskSlots per particle: the density sweep
+    // records the windows of candidate tests, the force sweep replays them.
+    uint64_t *masks;
 };
+
+constexpr int kMaskSlots = 16;
 
 // Sweep implementations: one thread per particle walking its own cell stencil, or one
 // workgroup per 2x2x2-cell brick with the brick's neighbourhood staged in LDS.
