@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2405_03980_amd", "tuned.json"))
+    ap.add_argument("--batch-steps", type=int, default=20,
+                    help="steps of the batched 64-instance ensemble (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="only run a plain device-to-device copy of this size (5 times), to "
                          "calibrate the HBM traffic counters, and exit")
@@ -74,12 +76,17 @@ def copy_calibration(mib: int) -> None:
     print(json.dumps({"copy_calibration_MiB": mib, "bytes_per_copy": 4 * n}), flush=True)
 
 
+TUNING_KEYS = ("block_density", "block_force", "block_stream", "use_graph", "sweep")
+
+
 def load_tuning(path, name):
+    """Tuned settings of a workload: (launch tuning for sph_tuning, cell factor)."""
     try:
         with open(path) as f:
-            return json.load(f).get(name, {})
+            t = json.load(f).get(name, {})
     except (OSError, ValueError):
-        return {}
+        t = {}
+    return {k: v for k, v in t.items() if k in TUNING_KEYS}, int(t.get("cell_factor", 1))
 
 
 def cpu_baseline(nz: int, steps: int) -> dict:
@@ -98,6 +105,94 @@ def cpu_baseline(nz: int, steps: int) -> dict:
             "kind": "oracle",
             "sample": f"{steps} steps of an {layers}-layer z-slab ({w.n} particles) of the "
                       f"nz={nz} cylinder, FP64, {dt:.1f} s"}
+
+
+def kernel_source_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "sph_device.h"):
+        with open(os.path.join(ROOT, "paper_2405_03980_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel calibration), or None when the
+    kernel source has changed since the counters were taken."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "counters.json")) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("source_sha") != kernel_source_sha() or kernel not in c.get("kernels", {}):
+        return None
+    k = c["kernels"][kernel]
+    return 1024.0 * (k["FETCH_SIZE_KiB"] * c["fetch_scale"] + k["WRITE_SIZE_KiB"] * c["write_scale"])
+
+
+def batch_bench(steps: int, tuning_path: str) -> dict:
+    """The 64-instance ensemble (20k-300k particles each, viscous fraction 0.05-0.5,
+    Omega 0.5-2), FP32-mixed: all instances in shared launches replayed from a hipGraph,
+    against the same instances stepped one after another."""
+    import torch
+    from paper_2405_03980_amd import inputs as I
+    from paper_2405_03980_amd import sim as S
+    ws = I.make_batch(64)
+    tun, cf = load_tuning(tuning_path, "batch64")
+    for w in ws:
+        w.params = dict(w.params, cell_factor=cf)
+    Om = [w.Omega for w in ws]
+    N = sum(w.n for w in ws)
+    b = S.batch_from(ws)
+    if tun:
+        b.set_tuning(**tun)
+    b.step(1e-4, Om, 4)
+    b.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(1e-4, Om, steps)
+    b.sync()
+    el = time.perf_counter() - t0
+    b.close()
+    del b
+    seq_steps = max(2, steps // 4)
+    sims = [S.simulation_from(w) for w in ws]
+    for s_, w in zip(sims, ws):
+        s_.step(1e-4, w.Omega, 2)
+    for s_ in sims:
+        s_.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(seq_steps):
+        for s_, w in zip(sims, ws):
+            s_.step(1e-4, w.Omega, 1)
+    for s_ in sims:
+        s_.sync()
+    el_seq = time.perf_counter() - t0
+    for s_ in sims:
+        s_.close()
+    del sims
+    torch.cuda.empty_cache()
+    ms = 1e3 * el / steps
+    ms_seq = 1e3 * el_seq / seq_steps
+    return {"value": N * steps / el, "unit": "particle-updates/s", "n_inst": len(ws),
+            "tuning": tun or "default", "cell_factor": cf,
+            "particles": N, "ms_per_step": round(ms, 3), "sequential_ms_per_step": round(ms_seq, 3),
+            "speedup_vs_sequential": round(ms_seq / ms, 2)}
+
+
+def field_errors(a: dict, b: dict, fluid) -> dict:
+    """Normwise relative difference of a against b over fluid particles."""
+    out = {}
+    for k in ("rho", "P", "v", "omega", "acc"):
+        x, y = a[k][..., fluid], b[k][..., fluid]
+        if x.ndim == 2:
+            d, r = np.sqrt(((x - y) ** 2).sum(0)), np.sqrt((y * y).sum(0))
+        else:
+            d, r = np.abs(x - y), np.abs(y)
+        out[k] = float(d.max() / max(r.max(), 1e-300))
+    return out
 
 
 def main():
@@ -120,9 +215,11 @@ def main():
     print(f"[bench] {name}: {n} particles ({nf} fluid)", file=sys.stderr, flush=True)
 
     def run(precision, steps, warmup, tuning):
-        s = S.simulation_from(w, precision=precision)
-        if tuning:
-            s.set_tuning(**tuning)
+        tun, cf = tuning
+        s = S.Simulation(dict(w.params, cell_factor=cf), w.n, precision=precision)
+        s.init(w.x, w.v, w.omega, w.species, w.kind)
+        if tun:
+            s.set_tuning(**tun)
         s.step(1e-4, w.Omega, warmup)
         s.sync()
         torch.cuda.synchronize()
@@ -133,13 +230,14 @@ def main():
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         s.sync()
+        fields = s.read(("rho", "P", "v", "omega", "acc"))
         s.close()
         del s
         torch.cuda.empty_cache()
-        return elapsed, ms, nsteps
+        return elapsed, ms, nsteps, fields
 
     tuning = load_tuning(args.tuning, name)
-    elapsed, ms, nsteps = run(L.FP32_MIXED, args.steps, args.warmup, tuning)
+    elapsed, ms, nsteps, f_mixed = run(L.FP32_MIXED, args.steps, args.warmup, tuning)
     assert nsteps == args.steps
     ms_step = 1e3 * elapsed / args.steps
     value = n * args.steps / elapsed
@@ -165,15 +263,27 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_frac, 4)}
-    roof.update({"kernel": dom, "avg_ms": round(per[dom], 4), "traffic": None,
+    traffic = measured_traffic(dom)
+    roof.update({"kernel": dom, "avg_ms": round(per[dom], 4),
+                 "traffic": None if traffic is None else round(traffic / 1e9, 3),
+                 "traffic_unit": "GB per launch",
                  "hbm_GBs": round(hbm, 1), "hbm_frac": round(hbm_frac, 4)})
 
     fp64 = None
     if args.fp64_steps > 0:
-        e64, ms64, n64 = run(L.FP64, args.fp64_steps, 2, tuning)
-        fp64 = {"ms_per_step": round(1e3 * e64 / args.fp64_steps, 3),
-                "speedup_mixed_vs_fp64": round((e64 / args.fp64_steps) / (elapsed / args.steps), 3)}
-        print(f"[bench] fp64: {fp64['ms_per_step']} ms/step", file=sys.stderr, flush=True)
+        # the FP64 path runs the same warmup + timed step count, so that the fields of
+        # both paths are compared after the same trajectory length
+        n64 = args.fp64_steps
+        e64, ms64, _, f64 = run(L.FP64, n64, args.warmup + args.steps - n64, tuning)
+        fp64 = {"ms_per_step": round(1e3 * e64 / n64, 3),
+                "speedup_mixed_vs_fp64": round((e64 / n64) / (elapsed / args.steps), 3),
+                "mixed_error_vs_fp64": field_errors(f_mixed, f64, w.kind == I.FLUID),
+                "after_steps": args.warmup + args.steps}
+        print(f"[bench] fp64: {fp64['ms_per_step']} ms/step; mixed vs fp64 "
+              f"{fp64['mixed_error_vs_fp64']}", file=sys.stderr, flush=True)
+    batch = batch_bench(args.batch_steps, args.tuning) if args.batch_steps > 0 else None
+    if batch:
+        print(f"[bench] batch: {batch}", file=sys.stderr, flush=True)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.nz, args.cpu_steps)
     line = {
@@ -183,10 +293,12 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"rotating cylinder, {n} particles ({nf} fluid), dx=1/{args.nz}, "
                                "Wendland C2, FP32-mixed, dt=1e-4",
-                   "particles": n, "precision": "fp32_mixed", "tuning": tuning or "default"},
+                   "particles": n, "precision": "fp32_mixed",
+                   "tuning": tuning[0] or "default", "cell_factor": tuning[1]},
         "kernel_ms": {k: round(v, 4) for k, v in per.items()},
         "roofline": roof,
         "fp64_gpu": fp64,
+        "batch64": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
