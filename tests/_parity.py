@@ -22,6 +22,12 @@ def min_image(d, params):
     return d
 
 
+def positions_ok(e: dict, tol: float, steps: int) -> bool:
+    """Displacement within tol, or positions within 2 ulps per step (rounding-limited:
+    the drift x + dt v is rounded once per step, fused on the GPU, twice in the oracle)."""
+    return e["x"] < tol or e["x_ulp"] <= 2 * max(steps, 1)
+
+
 def field_errors(out: dict, ref, w, x0=None) -> dict:
     """out: fields read from the library; ref: oracle State (same particles, by id)."""
     f = w.kind == 0
@@ -33,6 +39,9 @@ def field_errors(out: dict, ref, w, x0=None) -> dict:
     disp_ref = min_image(ref.x - x0, p)[:, f]
     dx = min_image(out["x"] - ref.x, p)[:, f]
     e["x"] = float(_norm(dx).max() / max(_norm(disp_ref).max(), 1e-300))
+    # the same difference in units of the coordinates' own spacing (ulp): positions cannot
+    # agree better than their rounding, whatever the displacement
+    e["x_ulp"] = float((np.abs(dx) / np.spacing(np.abs(ref.x[:, f]))).max())
     for k, r in (("v", ref.v), ("omega", ref.omega), ("acc", ref.acc), ("alpha", ref.alpha),
                  ("rho", ref.rho)):
         if k in out:

@@ -88,10 +88,17 @@ def test_workspace_grows_with_particles():
     a = _ws_status(p, 1000)[1]
     b = _ws_status(p, 100000)[1]
     assert 0 < a < b
-    p64 = L.make_params(w.params, L.FP64)
-    nb = C.c_size_t(0)
-    L.lib().sph_workspace_bytes(C.byref(p64), C.c_int64(100000), C.byref(nb))
-    assert nb.value > b
+    # without brick sweeps (cell factor 2) the FP64 state is the larger one; with them the
+    # mixed path also keeps 16 hit-mask words per particle
+    w2 = I.make_cylinder(10, cell_factor=2)
+    sizes = {}
+    for prec in (L.FP64, L.FP32_MIXED):
+        nb = C.c_size_t(0)
+        assert L.lib().sph_workspace_bytes(C.byref(L.make_params(w2.params, prec)), C.c_int64(100000),
+                                           C.byref(nb)) == L.OK
+        sizes[prec] = nb.value
+    assert sizes[L.FP64] > sizes[L.FP32_MIXED]
+    assert b > sizes[L.FP32_MIXED]
 
 
 @pytest.mark.parametrize("case", ["box", "cylinder", "cluster", "box_cf2", "cyl_cf3"])

@@ -1,0 +1,176 @@
+"""Parity at the full sizes of the measured workloads, in the launch configuration the
+benchmark times (the tuned settings of paper_2405_03980_amd/tuned.json).
+
+2.45M-particle cylinder: every fluid particle against the oracle after full steps.
+19.57M-particle cylinder: sampled particles against the oracle evaluated one by one, and
+one full step of every particle.  64-instance batch: every instance against its own
+single-instance run.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2405_03980_amd import _lib as L
+from paper_2405_03980_amd import inputs as I
+from tests._parity import field_errors, positions_ok
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KEYS = ("block_density", "block_force", "block_stream", "use_graph", "sweep")
+
+
+def _tuned(name):
+    with open(os.path.join(ROOT, "paper_2405_03980_amd", "tuned.json")) as f:
+        t = json.load(f).get(name, {})
+    return {k: v for k, v in t.items() if k in KEYS}, int(t.get("cell_factor", 1))
+
+
+def _sim(w, prec, name):
+    from paper_2405_03980_amd import sim as S
+    tun, cf = _tuned(name)
+    s = S.Simulation(dict(w.params, cell_factor=cf), w.n, precision=prec)
+    s.init(w.x, w.v, w.omega, w.species, w.kind)
+    if tun:
+        s.set_tuning(**tun)
+    return s
+
+
+@pytest.fixture(scope="module")
+def cyl245():
+    w = I.config(1)
+    print(f"[full] cylinder 2.45M: n={w.n}", flush=True)
+    ref = O.State.from_workload(w)
+    init = {k: getattr(ref, k).copy() for k in ("rho", "P", "acc", "alpha")}
+    ref.step(1e-4, w.Omega, 1)
+    one = {k: getattr(ref, k).copy() for k in ("x", "v", "omega", "rho", "P", "acc", "alpha")}
+    ref.step(1e-4, w.Omega, 1)
+    return w, init, one, ref
+
+
+class _Snap:
+    def __init__(self, d):
+        self.__dict__.update(d)
+
+
+def test_cylinder_2p45M_fp64_two_steps(cyl245):
+    w, init, one, ref2 = cyl245
+    s = _sim(w, L.FP64, "cylinder_nz92")
+    out0 = s.read(("rho", "P", "acc", "alpha"))
+    for k in ("rho", "acc", "alpha"):
+        f = w.kind == I.FLUID
+        e = np.abs(out0[k][..., f] - init[k][..., f]).max() / np.abs(init[k][..., f]).max()
+        assert e < 1e-12, (k, e)
+    s.step(1e-4, w.Omega, 2)
+    e = field_errors(s.read(), ref2, w)
+    print("2.45M fp64 2 steps", e, flush=True)
+    assert positions_ok(e, 1e-12, 2), e
+    for k in ("v", "omega", "rho", "P", "acc", "alpha"):
+        assert e[k] < 1e-12, (k, e[k])
+    s.close()
+
+
+def test_cylinder_2p45M_mixed_one_step(cyl245):
+    w, init, one, _ = cyl245
+    s = _sim(w, L.FP32_MIXED, "cylinder_nz92")
+    s.step(1e-4, w.Omega, 1)
+    e = field_errors(s.read(), _Snap(one), w)
+    print("2.45M mixed 1 step", e, flush=True)
+    assert positions_ok(e, 1e-5, 1), e
+    for k in ("v", "omega", "rho", "P"):
+        assert e[k] < 1e-5, (k, e[k])
+    s.close()
+
+
+@pytest.fixture(scope="module")
+def cyl1957():
+    w = I.config(3)
+    print(f"[full] cylinder 19.57M: n={w.n}", flush=True)
+    return w
+
+
+def test_cylinder_19p57M_sampled_initial_fields(cyl1957):
+    """The benchmarked configuration: sampled particles against the oracle's one-by-one
+    evaluation (density of the sample and its neighbours, then their forces)."""
+    w = cyl1957
+    rng = np.random.default_rng(11)
+    fluid = np.nonzero(w.kind == I.FLUID)[0]
+    near_wall = fluid[np.hypot(w.x[0, fluid], w.x[1, fluid]) > 1.0 - 6 * w.params["dx"]]
+    idx = np.unique(np.concatenate([rng.choice(fluid, 2000, replace=False),
+                                    rng.choice(near_wall, 1000, replace=False)]))
+    rho, P, S_, acc, alpha = O.eval_subset(w.params, w.x, w.v, w.omega, w.species, w.kind, idx)
+    B = w.params["rho0"] * w.params["c0"] ** 2 / 7.0
+    for prec, tol in ((L.FP32_MIXED, 1e-5), (L.FP64, 1e-12)):
+        s = _sim(w, prec, "cylinder_nz184")
+        out = s.read(("rho", "P", "acc", "alpha"))
+        s.close()
+        del s
+        e_rho = np.abs(out["rho"][idx] - rho).max() / np.abs(rho).max()
+        e_P = np.abs(out["P"][idx] - P).max() / B
+        na = np.sqrt((acc ** 2).sum(0)).max()
+        e_acc = np.sqrt(((out["acc"][:, idx] - acc) ** 2).sum(0)).max() / na
+        nl = np.sqrt((alpha ** 2).sum(0)).max()
+        e_al = np.sqrt(((out["alpha"][:, idx] - alpha) ** 2).sum(0)).max() / nl
+        print(f"19.57M sampled prec={prec}: rho {e_rho:.2e} P {e_P:.2e} acc {e_acc:.2e} alpha {e_al:.2e}",
+              flush=True)
+        assert max(e_rho, e_P, e_acc, e_al) < tol
+
+
+def test_cylinder_19p57M_mixed_one_step(cyl1957):
+    w = cyl1957
+    s = _sim(w, L.FP32_MIXED, "cylinder_nz184")
+    s.step(1e-4, w.Omega, 1)
+    out = s.read(("x", "v", "omega", "rho", "P"))
+    s.close()
+    del s
+    ref = O.State.from_workload(w)
+    ref.step(1e-4, w.Omega, 1)
+    e = field_errors(out, ref, w)
+    print("19.57M mixed 1 step", e, flush=True)
+    assert positions_ok(e, 1e-5, 1), e
+    for k in ("v", "omega", "rho", "P"):
+        assert e[k] < 1e-5, (k, e[k])
+
+
+def test_batch64_equals_single_instances():
+    """The 64-instance ensemble (5.9M particles) in its tuned launch configuration equals,
+    bit for bit, each instance run on its own with the same settings."""
+    from paper_2405_03980_amd import sim as S
+    ws = I.make_batch(64)
+    tun, cf = _tuned("batch64")
+    for w in ws:
+        w.params = dict(w.params, cell_factor=cf)
+    b = S.batch_from(ws)
+    if tun:
+        b.set_tuning(**tun)
+    Om = [w.Omega for w in ws]
+    b.step(1e-4, Om, 4)
+    out = b.read(("x", "v", "omega", "rho"))
+    b.close()
+    del b
+    for i in (0, 7, 23, 63):
+        w = ws[i]
+        s = S.simulation_from(w)
+        if tun:
+            s.set_tuning(**tun)
+        s.step(1e-4, w.Omega, 4)
+        o = s.read(("x", "v", "omega", "rho"))
+        s.close()
+        lo = sum(x.n for x in ws[:i])
+        for k in o:
+            assert np.array_equal(out[k][..., lo:lo + w.n], o[k]), (i, k)
+    # and two instances against the oracle
+    for i in (3, 40):
+        w = ws[i]
+        ref = O.State.from_workload(w)
+        ref.step(1e-4, w.Omega, 4)
+        lo = sum(x.n for x in ws[:i])
+        part = {k: out[k][..., lo:lo + w.n] for k in out}
+        e = field_errors(part, ref, w)
+        print(f"batch instance {i} n={w.n}", e, flush=True)
+        assert positions_ok(e, 1e-5, 4), e
+        for k in ("v", "omega", "rho"):
+            assert e[k] < 1e-5, (i, k, e[k])

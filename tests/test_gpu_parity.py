@@ -11,7 +11,7 @@ import pytest
 from oracle import oracle as O
 from paper_2405_03980_amd import _lib as L
 from paper_2405_03980_amd import inputs as I
-from tests._parity import field_errors
+from tests._parity import field_errors, positions_ok
 
 pytestmark = pytest.mark.gpu
 
@@ -93,7 +93,8 @@ def test_box4096_fp64_20_steps():
     s.step(w.dt, w.Omega, w.steps)
     e = field_errors(s.read(), ref, w)
     print("box4096 fp64 20 steps", e, flush=True)
-    assert max(e.values()) < 1e-12
+    assert positions_ok(e, 1e-12, w.steps)
+    assert max(v for k, v in e.items() if not k.startswith("x")) < 1e-12
     s.close()
 
 
@@ -107,7 +108,8 @@ def test_cylinder_steps(prec, steps, tol):
     s.step(1e-4, w.Omega, steps)
     e = field_errors(s.read(), ref, w)
     print(e, flush=True)
-    for k in ("x", "v", "omega", "rho", "P"):
+    assert positions_ok(e, tol, steps), e
+    for k in ("v", "omega", "rho", "P"):
         assert e[k] < tol, (k, e[k])
     s.close()
 
@@ -214,7 +216,8 @@ def test_resume_from_checkpoint():
     ref.step(1e-4, 1.0, 10)
     e = field_errors(out, ref, w)
     print("resume", e, flush=True)
-    for k in ("x", "v", "omega", "rho", "P"):
+    assert positions_ok(e, 1e-12, 20), e
+    for k in ("v", "omega", "rho", "P"):
         assert e[k] < 1e-12, (k, e[k])
     for s in (half, res):
         s.close()
@@ -291,4 +294,60 @@ def test_brick_fallback_when_cells_are_full(h_factor):
     print("fallback", h_factor, e, flush=True)
     for k in ("rho", "P", "acc", "alpha"):
         assert e[k] < 1e-5, (k, e[k])
+    s.close()
+
+
+@pytest.mark.parametrize("prec", [FP64, MIXED])
+def test_single_particle_is_ballistic(prec):
+    x = np.array([[0.4], [0.5], [0.6]])
+    v = np.array([[0.3], [-0.2], [0.1]])
+    p = I.base_params(I.KERNEL_WENDLAND_C2, I.GEOM_OPEN, 0.05, [0, 0, 0], [1, 1, 1], 1.0)
+    from paper_2405_03980_amd import sim as S
+    s = S.Simulation(p, 1, precision=prec)
+    s.init(x, v, np.zeros((3, 1)), np.zeros(1, np.uint8), np.zeros(1, np.uint8))
+    s.step(1e-3, 0.0, 100)
+    out = s.read()
+    assert np.allclose(out["x"], x + 0.1 * v, rtol=0, atol=1e-14)
+    assert np.array_equal(out["v"], v) and np.all(out["acc"] == 0)
+    rho_self = O.default_mass(p)[0] * O.W(p["kernel"], p["h"], 0.0)
+    assert abs(out["rho"][0] - rho_self) < (1e-12 if prec == FP64 else 1e-6) * rho_self
+    s.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(FP64, 1e-12), (MIXED, 1e-5)])
+def test_two_particles(prec, tol):
+    x = np.array([[0.5, 0.5 + 0.031], [0.5, 0.5 + 0.012], [0.5, 0.5 - 0.007]])
+    v = np.array([[0.1, -0.2], [0.0, 0.3], [0.05, 0.0]])
+    om = np.array([[0.0, 1.0], [2.0, 0.0], [0.5, -0.5]])
+    p = I.base_params(I.KERNEL_WENDLAND_C2, I.GEOM_OPEN, 0.03, [0, 0, 0], [1, 1, 1], 1.0)
+    p["sigma_T"], p["C_l"], p["eta"] = 0.2, 0.3, 0.05
+    sp = np.array([0, 1], np.uint8)
+    kd = np.zeros(2, np.uint8)
+    from paper_2405_03980_amd import sim as S
+    s = S.Simulation(p, 2, precision=prec)
+    s.init(x, v, om, sp, kd)
+    s.step(1e-4, 0.0, 3)
+    out = s.read()
+    ref = O.State(p, x, v, om, sp, kd)
+    ref.step(1e-4, 0.0, 3)
+    for k in ("v", "omega", "rho", "acc", "alpha"):
+        r = getattr(ref, k)
+        assert np.abs(out[k] - r).max() <= tol * np.abs(r).max(), k
+    s.close()
+
+
+@pytest.mark.parametrize("visc_frac", [0.0, 1.0])
+@pytest.mark.parametrize("prec,tol", [(FP64, 1e-12), (MIXED, 1e-5)])
+def test_single_species_mixture(visc_frac, prec, tol):
+    """No unlike pairs (S = 0 everywhere) or only viscous pairs."""
+    w = I.make_cylinder(12, visc_frac=visc_frac)
+    ref = O.State.from_workload(w)
+    ref.step(1e-4, w.Omega, 5)
+    s = _sim(w, prec)
+    s.step(1e-4, w.Omega, 5)
+    e = field_errors(s.read(), ref, w)
+    print("single species", visc_frac, prec, e, flush=True)
+    assert positions_ok(e, tol, 5), e
+    for k in ("v", "omega", "rho", "P"):
+        assert e[k] < tol, (k, e[k])
     s.close()
