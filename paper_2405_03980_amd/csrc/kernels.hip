@@ -627,6 +627,7 @@ __global__ void k_force(DevState s)
 constexpr int kBrickThreads = 512;
 constexpr int kStageDensity = 2048;
 constexpr int kStageForce = 1408;
+constexpr int kMergeWin = 4;  // windows whose hits a lane processes as one stream
 
 struct BrickFrame {
     uint32_t begin[64];   // sorted index of each slot's first particle
@@ -634,12 +635,19 @@ struct BrickFrame {
     double shift[64][3];  // periodic image shift of each slot
     double origin[3];     // brick centre
     uint32_t ok;          // 0: too many particles to stage (per-thread fallback)
-    int32_t win[kBrickThreads / 64][64];  // per wave: candidate = win[bit] + g + G * bit
+    // per wave, for the (up to kMergeWin) windows being processed: candidate of bit j of
+    // window c = win[c][j] + g + G * j
+    int16_t win[kBrickThreads / 64][4][64];
 };
 
-// Fills the frame (threads 0..63) and returns the staged particle count.
+__device__ __forceinline__ int slot_index(int x, int y, int z) { return x + 4 * (y + 4 * z); }
+
+// Fills the frame (wave 0: one lane per slot, a wave-level scan for the offsets) and
+// returns the staged particle count.  With Vv, the lane of slot (1,1,1), the brick's
+// first cell, also loads the velocity of that cell's first particle into vref.
 __device__ __forceinline__ uint32_t brick_frame(const DevState &s, const InstDesc *d, uint32_t bxyz,
-                                                BrickFrame &F, int stage_max)
+                                                BrickFrame &F, int stage_max,
+                                                const double *Vv = nullptr, double *vref = nullptr)
 {
     const int t = threadIdx.x;
     const int b[3] = {(int)(bxyz & 1023), (int)((bxyz >> 10) & 1023), (int)(bxyz >> 20)};
@@ -666,21 +674,18 @@ __device__ __forceinline__ uint32_t brick_frame(const DevState &s, const InstDes
             cnt = s.start[r + 1] - beg;
         }
         F.begin[t] = beg;
-        F.off[t + 1] = cnt;  // counts; prefix taken below
-        if (t < 3) F.origin[t] = d->lo[t] + (double)(2 * b[t] + 1) * d->edge[t];
-    }
-    __syncthreads();
-    if (t == 0) {
-        uint32_t acc = 0;
-        bool ok = true;
-        F.off[0] = 0;
-        for (int k = 0; k < 64; k++) {
-            uint32_t c = F.off[k + 1];
-            if (c > (uint32_t)kMaxCell) ok = false;
-            acc += c;
-            F.off[k + 1] = acc;
+        uint32_t inc = cnt;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(inc, o);
+            if (t >= o) inc += y;
         }
-        F.ok = ok && acc <= (uint32_t)stage_max;
+        F.off[t + 1] = inc;
+        if (t == 0) F.off[0] = 0;
+        const bool over = __any(cnt > (uint32_t)kMaxCell);
+        if (t == 63) F.ok = !over && inc <= (uint32_t)stage_max;
+        if (t < 3) F.origin[t] = d->lo[t] + (double)(2 * b[t] + 1) * d->edge[t];
+        if (Vv && t == slot_index(1, 1, 1))
+            for (int a = 0; a < 3; a++) vref[a] = cnt ? Vv[(size_t)a * s.N + beg] : 0.0;
     }
     __syncthreads();
     return F.off[64];
@@ -711,7 +716,6 @@ __device__ __forceinline__ bool brick_target(const InstDesc *d, uint32_t bxyz, i
     return in;
 }
 
-__device__ __forceinline__ int slot_index(int x, int y, int z) { return x + 4 * (y + 4 * z); }
 
 // Sum of the G partial (Kahan) sums of a target, held by lanes t, t + ntc, ...
 __device__ __forceinline__ double group_total(float s_, float c_, int lane, int ntc, int G)
@@ -742,63 +746,70 @@ __device__ __forceinline__ bool masks_fit(const BrickFrame &F, const int ts[3], 
 // lane builds a 64-bit hit mask, bit t = trip t, either by test(k, in_row) (when in_row is
 // false, the group's last trip ran past its row, k is clamped into the row and the test
 // must return false) or, when `replay`, by loading the mask recorded by an earlier walk
-// from rec[window * G].  When `record`, the mask is stored to rec[window * G].  body(k) is
-// then called for every hit, two at a time (body2) so that their LDS loads overlap.  All
-// lanes of the wave execute the same window and trip sequence.
-template <class Test, class Body, class Body2>
-__device__ __forceinline__ void stencil_windows(const BrickFrame &F, int32_t *win, const int ts[3],
+// from rec[window * G].  When `record`, the mask is stored to rec[window * G].  After every
+// kMergeWin windows (and at the end) each lane calls body(k) for all hits of those windows
+// as one stream, so the wave waits for the lane with the most hits over several windows
+// rather than per window.  All lanes execute the same window and trip sequence.
+template <class Test, class Body>
+__device__ __forceinline__ void stencil_windows(const BrickFrame &F, int16_t (*win)[64], const int ts[3],
                                                 int lane, int g, int G, bool record, bool replay,
-                                                uint64_t *rec, Test &&test, Body &&body,
-                                                Body2 &&body2)
+                                                uint64_t *rec, Test &&test, Body &&body)
 {
-    int r = 0;          // current row (dz * 3 + dy)
+    int r = 0;          // current row (visiting order below)
     uint32_t done = 0;  // trips of row r already walked
     int wi = 0;         // window index
     while (r < 9) {
-        uint32_t mlo = 0, mhi = 0;
-        int W = 0;
-        while (r < 9 && W < 64) {
-            const int s0 = slot_index(ts[0] - 1, ts[1] - 1 + (r % 3), ts[2] - 1 + (r / 3));
-            const uint32_t b = F.off[s0], e = F.off[s0 + 3];
-            const uint32_t trips = (e - b + (uint32_t)G - 1) / (uint32_t)G;
-            const uint32_t take = min(trips - done, (uint32_t)(64 - W));
-            if (lane >= W && lane < W + (int)take)
-                win[lane] = (int32_t)(b + (uint32_t)G * done) - G * W;
-            if (!replay) {
-                const uint32_t kb = b + (uint32_t)g + (uint32_t)G * done;
+        uint64_t m[kMergeWin];
+        int nw = 0;
+        for (; nw < kMergeWin && r < 9; nw++, wi++) {
+            uint64_t tm = 0;
+            int W = 0;
+            while (r < 9 && W < 64) {
+                // rows in Latin-square order: every three consecutive rows cover all three
+                // z layers and all three y offsets, so each window holds a similar share of
+                // every target's neighbours whatever its position in the cell
+                const int dz = r % 3, dy = (r % 3 + r / 3) % 3;
+                const int s0 = slot_index(ts[0] - 1, ts[1] - 1 + dy, ts[2] - 1 + dz);
+                const uint32_t b = F.off[s0], e = F.off[s0 + 3];
+                const uint32_t trips = (e - b + (uint32_t)G - 1) / (uint32_t)G;
+                const uint32_t take = min(trips - done, (uint32_t)(64 - W));
+                if (lane >= W && lane < W + (int)take)
+                    win[nw][lane] = (int16_t)((int32_t)(b + (uint32_t)G * done) - G * W);
+                if (!replay) {
+                    const uint32_t kb = b + (uint32_t)g + (uint32_t)G * done;
 #pragma unroll 4
-                for (uint32_t t = 0; t < take; t++) {
-                    const uint32_t k = kb + (uint32_t)G * t;
-                    const bool in_row = k < e;
-                    const uint32_t bit = (uint32_t)test(in_row ? k : e - 1, in_row);
-                    const int pos = W + (int)t;
-                    if (pos < 32) mlo |= bit << pos;
-                    else mhi |= bit << (pos - 32);
+                    for (uint32_t t = 0; t < take; t++) {
+                        const uint32_t k = kb + (uint32_t)G * t;
+                        const uint64_t bit = test(min(k, e - 1), k < e) ? 1ull : 0ull;
+                        tm |= bit << (W + (int)t);
+                    }
                 }
+                W += (int)take;
+                done += take;
+                if (done == trips) { r++; done = 0; }
             }
-            W += (int)take;
-            done += take;
-            if (done == trips) { r++; done = 0; }
-        }
-        uint64_t mask;
-        if (replay) {
-            mask = rec ? rec[wi * G] : 0ull;
-        } else {
-            mask = ((uint64_t)mhi << 32) | mlo;
-            if (record && rec) rec[wi * G] = mask;
-        }
-        wi++;
-        __builtin_amdgcn_wave_barrier();
-        while (mask) {
-            const int j0 = __builtin_ctzll(mask);
-            mask &= mask - 1;
-            if (mask) {
-                const int j1 = __builtin_ctzll(mask);
-                mask &= mask - 1;
-                body2((uint32_t)(win[j0] + g + G * j0), (uint32_t)(win[j1] + g + G * j1));
+            uint64_t mask;
+            if (replay) {
+                mask = rec ? rec[wi * G] : 0ull;
             } else {
-                body((uint32_t)(win[j0] + g + G * j0));
+                mask = tm;
+                if (record && rec) rec[wi * G] = mask;
             }
+            m[nw] = mask;
+        }
+        __builtin_amdgcn_wave_barrier();
+        // one stream over the collected windows: c is the window of the remaining bits mc
+        int c = 0;
+        uint64_t mc = m[0];
+        while (true) {
+            while (mc == 0 && c + 1 < nw) {
+                c++;
+                mc = c == 1 ? m[1] : (c == 2 ? m[2] : m[3]);
+            }
+            if (mc == 0) break;
+            const int j = __builtin_ctzll(mc);
+            mc &= mc - 1;
+            body((uint32_t)((int32_t)win[c][j] + g + G * j));
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -882,15 +893,30 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_brick(DevState s)
         if (err) atomicOr(s.err, err);
         return;
     }
-    for (uint32_t k = threadIdx.x; k < M; k += kBrickThreads) {
-        const int sl = slot_of(F, k);
-        const uint32_t q = F.begin[sl] + (k - F.off[sl]);
-        float4 v;
-        v.x = (float)((X[q] + F.shift[sl][0]) - F.origin[0]);
-        v.y = (float)((X[N + q] + F.shift[sl][1]) - F.origin[1]);
-        v.z = (float)((X[2 * N + q] + F.shift[sl][2]) - F.origin[2]);
-        v.w = (float)(SK[q] & 1);
-        stage[k] = v;
+    // staging: each thread takes up to two candidates and issues all their loads first
+    for (uint32_t k0 = threadIdx.x; k0 < M; k0 += 2 * kBrickThreads) {
+        uint32_t kk[2], qq[2];
+        int sl[2];
+        for (int u = 0; u < 2; u++) {
+            kk[u] = k0 + (uint32_t)u * kBrickThreads;
+            sl[u] = slot_of(F, min(kk[u], M - 1));
+            qq[u] = F.begin[sl[u]] + (min(kk[u], M - 1) - F.off[sl[u]]);
+        }
+        double px[2][3];
+        uint8_t sk[2];
+        for (int u = 0; u < 2; u++) {
+            for (int a = 0; a < 3; a++) px[u][a] = X[(size_t)a * N + qq[u]];
+            sk[u] = SK[qq[u]];
+        }
+        for (int u = 0; u < 2; u++) {
+            if (kk[u] >= M) break;
+            float4 v;
+            v.x = (float)((px[u][0] + F.shift[sl[u]][0]) - F.origin[0]);
+            v.y = (float)((px[u][1] + F.shift[sl[u]][1]) - F.origin[1]);
+            v.z = (float)((px[u][2] + F.shift[sl[u]][2]) - F.origin[2]);
+            v.w = (float)(sk[u] & 1);
+            stage[kk[u]] = v;
+        }
     }
     __syncthreads();
     if (!has_cell) return;
@@ -903,7 +929,8 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_brick(DevState s)
         const int g = lane / ntc, t = lane % ntc;
         const bool active = g < G;
         const uint32_t kself = F.off[tslot] + chunk + t;
-        const float4 me = stage[active ? kself : F.off[tslot]];
+        float4 me = stage[active ? kself : F.off[tslot]];
+        if (!active) me.x = __builtin_inff();  // no candidate is within reach
         Acc<float, KAHAN> sw, su;
         auto wval = [&](const float4 &c) {
             const float d0 = me.x - c.x, d1 = me.y - c.y, d2 = me.z - c.z;
@@ -923,21 +950,13 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_brick(DevState s)
             [&](uint32_t k, bool in_row) {
                 const float4 c = stage[k];
                 const float d0 = me.x - c.x, d1 = me.y - c.y, d2 = me.z - c.z;
-                return in_row & active & (k != kself) & (d0 * d0 + d1 * d1 + d2 * d2 < cut2);
+                return in_row & (k != kself) & (d0 * d0 + d1 * d1 + d2 * d2 < cut2);
             },
             [&](uint32_t k) {
                 const float4 c = stage[k];
                 const float W = wval(c);
                 sw.add(W);
                 su.add(c.w != me.w ? W : 0.0f);
-            },
-            [&](uint32_t k0, uint32_t k1) {
-                const float4 c0 = stage[k0], c1 = stage[k1];
-                const float W0 = wval(c0), W1 = wval(c1);
-                sw.add(W0);
-                su.add(c0.w != me.w ? W0 : 0.0f);
-                sw.add(W1);
-                su.add(c1.w != me.w ? W1 : 0.0f);
             });
         const double SW = group_total(sw.s, KAHAN ? sw.c : 0.0f, lane, ntc, G);
         const double SU = group_total(su.s, KAHAN ? su.c : 0.0f, lane, ntc, G);
@@ -965,7 +984,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_force_brick(DevState s)
     const double *X = s.x[cur], *Vv = s.v[cur], *Ww = s.w[cur];
     const uint8_t *SK = s.sk[cur];
     const float *AUX = (const float *)s.aux;
-    const uint32_t M = brick_frame(s, d, bxyz, F, kStageForce);
+    const uint32_t M = brick_frame(s, d, bxyz, F, kStageForce, Vv, vref);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int ts[3];
     const bool has_cell = brick_target(d, bxyz, w, ts);
@@ -979,22 +998,38 @@ __global__ void __launch_bounds__(kBrickThreads) k_force_brick(DevState s)
         if (err) atomicOr(s.err, err);
         return;
     }
-    if (threadIdx.x < 3) {
-        const int c0 = slot_index(1, 1, 1);
-        vref[threadIdx.x] = F.off[c0 + 1] > F.off[c0] ? Vv[threadIdx.x * N + F.begin[c0]] : 0.0;
-    }
-    __syncthreads();
-    for (uint32_t k = threadIdx.x; k < M; k += kBrickThreads) {
-        const int sl = slot_of(F, k);
-        const uint32_t q = F.begin[sl] + (k - F.off[sl]);
-        const float4 aq = *(const float4 *)(AUX + 4 * (size_t)q);
-        const int sp = SK[q] & 1;
-        SA[k] = make_float4((float)((X[q] + F.shift[sl][0]) - F.origin[0]),
-                            (float)((X[N + q] + F.shift[sl][1]) - F.origin[1]),
-                            (float)((X[2 * N + q] + F.shift[sl][2]) - F.origin[2]), aq.y);
-        SB[k] = make_float4((float)(Vv[q] - vref[0]), (float)(Vv[N + q] - vref[1]),
-                            (float)(Vv[2 * N + q] - vref[2]), sp ? -aq.x : aq.x);
-        SC[k] = make_float4((float)Ww[q], (float)Ww[N + q], (float)Ww[2 * N + q], aq.w);
+    // staging: each thread takes up to three candidates and issues all their loads first
+    for (uint32_t k0 = threadIdx.x; k0 < M; k0 += 3 * kBrickThreads) {
+        uint32_t kk[3], qq[3];
+        int sl[3];
+        for (int u = 0; u < 3; u++) {
+            kk[u] = k0 + (uint32_t)u * kBrickThreads;
+            sl[u] = slot_of(F, min(kk[u], M - 1));
+            qq[u] = F.begin[sl[u]] + (min(kk[u], M - 1) - F.off[sl[u]]);
+        }
+        double px[3][3], pv[3][3], pw[3][3];
+        float4 aq[3];
+        uint8_t sk[3];
+        for (int u = 0; u < 3; u++) {
+            const uint32_t q = qq[u];
+            for (int a = 0; a < 3; a++) {
+                px[u][a] = X[(size_t)a * N + q];
+                pv[u][a] = Vv[(size_t)a * N + q];
+                pw[u][a] = Ww[(size_t)a * N + q];
+            }
+            aq[u] = *(const float4 *)(AUX + 4 * (size_t)q);
+            sk[u] = SK[q];
+        }
+        for (int u = 0; u < 3; u++) {
+            if (kk[u] >= M) break;
+            const uint32_t k = kk[u];
+            SA[k] = make_float4((float)((px[u][0] + F.shift[sl[u]][0]) - F.origin[0]),
+                                (float)((px[u][1] + F.shift[sl[u]][1]) - F.origin[1]),
+                                (float)((px[u][2] + F.shift[sl[u]][2]) - F.origin[2]), aq[u].y);
+            SB[k] = make_float4((float)(pv[u][0] - vref[0]), (float)(pv[u][1] - vref[1]),
+                                (float)(pv[u][2] - vref[2]), (sk[u] & 1) ? -aq[u].x : aq[u].x);
+            SC[k] = make_float4((float)pw[u][0], (float)pw[u][1], (float)pw[u][2], aq[u].w);
+        }
     }
     __syncthreads();
     if (!has_cell) return;
@@ -1050,15 +1085,6 @@ __global__ void __launch_bounds__(kBrickThreads) k_force_brick(DevState s)
                 float f[3], n[3];
                 pair(SA[k], SB[k], SC[k], f, n);
                 accum(f, n);
-            },
-            [&](uint32_t k0, uint32_t k1) {
-                const float4 A0 = SA[k0], B0 = SB[k0], C0 = SC[k0];
-                const float4 A1 = SA[k1], B1 = SB[k1], C1 = SC[k1];
-                float f0[3], n0[3], f1[3], n1[3];
-                pair(A0, B0, C0, f0, n0);
-                pair(A1, B1, C1, f1, n1);
-                accum(f0, n0);
-                accum(f1, n1);
             });
         const double f0 = group_total(F0.s, KAHAN ? F0.c : 0.0f, lane, ntc, G);
         const double f1 = group_total(F1.s, KAHAN ? F1.c : 0.0f, lane, ntc, G);
