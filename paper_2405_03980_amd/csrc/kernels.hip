@@ -206,7 +206,22 @@ __global__ void k_keys(DevState s, int mode, double kick, double dt)
     uint32_t lin = (uint32_t)c0 + (uint32_t)d->n[0] * ((uint32_t)c1 + (uint32_t)d->n[1] * (uint32_t)c2);
     uint32_t key = s.rank_of_lin[d->cell_off + lin];
     s.key[p] = key;
-    s.slot[p] = atomicAdd(&s.count[key], 1u);
+    // One atomic per distinct key of the wavefront: particles arrive nearly cell-sorted, so
+    // neighbouring lanes mostly share a cell.  Lanes of a key take consecutive slots in lane
+    // order (the final in-cell order is fixed by id in k_reorder).
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint64_t todo = __ballot(1);
+    while (todo) {
+        const int leader = __builtin_ctzll(todo);
+        const uint32_t lk = __shfl(key, leader);
+        const uint64_t same = __ballot(key == lk) & todo;
+        uint32_t base = 0;
+        if ((int)lane == leader) base = atomicAdd(&s.count[lk], (uint32_t)__popcll(same));
+        base = __shfl(base, leader);
+        if (key == lk) s.slot[p] = base + (uint32_t)__popcll(same & below);
+        todo &= ~same;
+    }
     if (err) atomicOr(s.err, err);
 }
 
