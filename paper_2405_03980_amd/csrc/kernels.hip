@@ -650,10 +650,11 @@ struct BrickFrame {
     double shift[64][3];  // periodic image shift of each slot
     double origin[3];     // brick centre
     uint32_t ok;          // 0: too many particles to stage (per-thread fallback)
-    // per wave, for the (up to kMergeWin) windows being processed: candidate of bit j of
-    // window c = win[c][j] + g + G * j
-    int16_t win[kBrickThreads / 64][4][64];
 };
+
+// Per wave of the target-major sweeps, for the (up to kMergeWin) windows being processed:
+// candidate of bit j of window c = win[c][j] + g + G * j.
+typedef int16_t WindowTable[kBrickThreads / 64][kMergeWin][64];
 
 __device__ __forceinline__ int slot_index(int x, int y, int z) { return x + 4 * (y + 4 * z); }
 
@@ -743,6 +744,86 @@ __device__ __forceinline__ double group_total(float s_, float c_, int lane, int 
         tot += (double)a - (double)b;
     }
     return tot;
+}
+
+// Stages the positions of the brick's M neighbourhood particles relative to the brick
+// centre (FP64 difference, then FP32) and their species: each thread takes up to two
+// particles and issues all their loads first.
+__device__ __forceinline__ void stage_density(const DevState &s, const BrickFrame &F, uint32_t M,
+                                              float4 *stage)
+{
+    const uint32_t N = s.N;
+    const double *X = s.x[s.cur];
+    const uint8_t *SK = s.sk[s.cur];
+    for (uint32_t k0 = threadIdx.x; k0 < M; k0 += 2 * kBrickThreads) {
+        uint32_t kk[2], qq[2];
+        int sl[2];
+        for (int u = 0; u < 2; u++) {
+            kk[u] = k0 + (uint32_t)u * kBrickThreads;
+            sl[u] = slot_of(F, min(kk[u], M - 1));
+            qq[u] = F.begin[sl[u]] + (min(kk[u], M - 1) - F.off[sl[u]]);
+        }
+        double px[2][3];
+        uint8_t sk[2];
+        for (int u = 0; u < 2; u++) {
+            for (int a = 0; a < 3; a++) px[u][a] = X[(size_t)a * N + qq[u]];
+            sk[u] = SK[qq[u]];
+        }
+        for (int u = 0; u < 2; u++) {
+            if (kk[u] >= M) break;
+            float4 v;
+            v.x = (float)((px[u][0] + F.shift[sl[u]][0]) - F.origin[0]);
+            v.y = (float)((px[u][1] + F.shift[sl[u]][1]) - F.origin[1]);
+            v.z = (float)((px[u][2] + F.shift[sl[u]][2]) - F.origin[2]);
+            v.w = (float)(sk[u] & 1);
+            stage[kk[u]] = v;
+        }
+    }
+}
+
+// Stages what the force sweep reads of the brick's M neighbourhood particles: position
+// relative to the brick centre and P/rho^2; velocity relative to vref and V (negative for
+// the viscous species); spin and V/S.  Each thread takes up to three particles.
+__device__ __forceinline__ void stage_force(const DevState &s, const BrickFrame &F, uint32_t M,
+                                            const double *vref, float4 *SA, float4 *SB, float4 *SC)
+{
+    const uint32_t N = s.N;
+    const int cur = s.cur;
+    const double *X = s.x[cur], *Vv = s.v[cur], *Ww = s.w[cur];
+    const uint8_t *SK = s.sk[cur];
+    const float *AUX = (const float *)s.aux;
+    for (uint32_t k0 = threadIdx.x; k0 < M; k0 += 3 * kBrickThreads) {
+        uint32_t kk[3], qq[3];
+        int sl[3];
+        for (int u = 0; u < 3; u++) {
+            kk[u] = k0 + (uint32_t)u * kBrickThreads;
+            sl[u] = slot_of(F, min(kk[u], M - 1));
+            qq[u] = F.begin[sl[u]] + (min(kk[u], M - 1) - F.off[sl[u]]);
+        }
+        double px[3][3], pv[3][3], pw[3][3];
+        float4 aq[3];
+        uint8_t sk[3];
+        for (int u = 0; u < 3; u++) {
+            const uint32_t q = qq[u];
+            for (int a = 0; a < 3; a++) {
+                px[u][a] = X[(size_t)a * N + q];
+                pv[u][a] = Vv[(size_t)a * N + q];
+                pw[u][a] = Ww[(size_t)a * N + q];
+            }
+            aq[u] = *(const float4 *)(AUX + 4 * (size_t)q);
+            sk[u] = SK[q];
+        }
+        for (int u = 0; u < 3; u++) {
+            if (kk[u] >= M) break;
+            const uint32_t k = kk[u];
+            SA[k] = make_float4((float)((px[u][0] + F.shift[sl[u]][0]) - F.origin[0]),
+                                (float)((px[u][1] + F.shift[sl[u]][1]) - F.origin[1]),
+                                (float)((px[u][2] + F.shift[sl[u]][2]) - F.origin[2]), aq[u].y);
+            SB[k] = make_float4((float)(pv[u][0] - vref[0]), (float)(pv[u][1] - vref[1]),
+                                (float)(pv[u][2] - vref[2]), (sk[u] & 1) ? -aq[u].x : aq[u].x);
+            SC[k] = make_float4((float)pw[u][0], (float)pw[u][1], (float)pw[u][2], aq[u].w);
+        }
+    }
 }
 
 // Trips of the stencil walk of the wave's target cell (rows split over G groups) and
@@ -887,13 +968,11 @@ template <bool KAHAN>
 __global__ void __launch_bounds__(kBrickThreads) k_density_brick(DevState s)
 {
     __shared__ BrickFrame F;
+    __shared__ WindowTable win;
     __shared__ float4 stage[kStageDensity];
     const uint32_t bxyz = s.brick_xyz[blockIdx.x];
     const InstDesc *d = s.desc + s.brick_inst[blockIdx.x];
-    const uint32_t N = s.N;
-    const int cur = s.cur;
-    const double *X = s.x[cur];
-    const uint8_t *SK = s.sk[cur];
+    const uint8_t *SK = s.sk[s.cur];
     const uint32_t M = brick_frame(s, d, bxyz, F, kStageDensity);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int ts[3];
@@ -908,31 +987,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_brick(DevState s)
         if (err) atomicOr(s.err, err);
         return;
     }
-    // staging: each thread takes up to two candidates and issues all their loads first
-    for (uint32_t k0 = threadIdx.x; k0 < M; k0 += 2 * kBrickThreads) {
-        uint32_t kk[2], qq[2];
-        int sl[2];
-        for (int u = 0; u < 2; u++) {
-            kk[u] = k0 + (uint32_t)u * kBrickThreads;
-            sl[u] = slot_of(F, min(kk[u], M - 1));
-            qq[u] = F.begin[sl[u]] + (min(kk[u], M - 1) - F.off[sl[u]]);
-        }
-        double px[2][3];
-        uint8_t sk[2];
-        for (int u = 0; u < 2; u++) {
-            for (int a = 0; a < 3; a++) px[u][a] = X[(size_t)a * N + qq[u]];
-            sk[u] = SK[qq[u]];
-        }
-        for (int u = 0; u < 2; u++) {
-            if (kk[u] >= M) break;
-            float4 v;
-            v.x = (float)((px[u][0] + F.shift[sl[u]][0]) - F.origin[0]);
-            v.y = (float)((px[u][1] + F.shift[sl[u]][1]) - F.origin[1]);
-            v.z = (float)((px[u][2] + F.shift[sl[u]][2]) - F.origin[2]);
-            v.w = (float)(sk[u] & 1);
-            stage[kk[u]] = v;
-        }
-    }
+    stage_density(s, F, M, stage);
     __syncthreads();
     if (!has_cell) return;
     const uint32_t nt = F.off[tslot + 1] - F.off[tslot];
@@ -961,7 +1016,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_brick(DevState s)
         };
         const bool rec_ok = masks_fit(F, ts, G);
         uint64_t *rec = (rec_ok && active) ? s.masks + (size_t)(F.begin[tslot] + chunk + t) * kMaskSlots + g : nullptr;
-        stencil_windows(F, F.win[w], ts, lane, active ? g : 0, G, rec_ok, false, rec,
+        stencil_windows(F, win[w], ts, lane, active ? g : 0, G, rec_ok, false, rec,
             [&](uint32_t k, bool in_row) {
                 const float4 c = stage[k];
                 const float d0 = me.x - c.x, d1 = me.y - c.y, d2 = me.z - c.z;
@@ -988,18 +1043,15 @@ template <bool KAHAN>
 __global__ void __launch_bounds__(kBrickThreads) k_force_brick(DevState s)
 {
     __shared__ BrickFrame F;
+    __shared__ WindowTable win;
     __shared__ float4 SA[kStageForce];   // position (brick frame), P/rho^2
     __shared__ float4 SB[kStageForce];   // velocity - v_ref, V (negative: viscous species)
     __shared__ float4 SC[kStageForce];   // spin, V/S
     __shared__ double vref[3];
     const uint32_t bxyz = s.brick_xyz[blockIdx.x];
     const InstDesc *d = s.desc + s.brick_inst[blockIdx.x];
-    const uint32_t N = s.N;
-    const int cur = s.cur;
-    const double *X = s.x[cur], *Vv = s.v[cur], *Ww = s.w[cur];
-    const uint8_t *SK = s.sk[cur];
-    const float *AUX = (const float *)s.aux;
-    const uint32_t M = brick_frame(s, d, bxyz, F, kStageForce, Vv, vref);
+    const uint8_t *SK = s.sk[s.cur];
+    const uint32_t M = brick_frame(s, d, bxyz, F, kStageForce, s.v[s.cur], vref);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int ts[3];
     const bool has_cell = brick_target(d, bxyz, w, ts);
@@ -1013,39 +1065,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_force_brick(DevState s)
         if (err) atomicOr(s.err, err);
         return;
     }
-    // staging: each thread takes up to three candidates and issues all their loads first
-    for (uint32_t k0 = threadIdx.x; k0 < M; k0 += 3 * kBrickThreads) {
-        uint32_t kk[3], qq[3];
-        int sl[3];
-        for (int u = 0; u < 3; u++) {
-            kk[u] = k0 + (uint32_t)u * kBrickThreads;
-            sl[u] = slot_of(F, min(kk[u], M - 1));
-            qq[u] = F.begin[sl[u]] + (min(kk[u], M - 1) - F.off[sl[u]]);
-        }
-        double px[3][3], pv[3][3], pw[3][3];
-        float4 aq[3];
-        uint8_t sk[3];
-        for (int u = 0; u < 3; u++) {
-            const uint32_t q = qq[u];
-            for (int a = 0; a < 3; a++) {
-                px[u][a] = X[(size_t)a * N + q];
-                pv[u][a] = Vv[(size_t)a * N + q];
-                pw[u][a] = Ww[(size_t)a * N + q];
-            }
-            aq[u] = *(const float4 *)(AUX + 4 * (size_t)q);
-            sk[u] = SK[q];
-        }
-        for (int u = 0; u < 3; u++) {
-            if (kk[u] >= M) break;
-            const uint32_t k = kk[u];
-            SA[k] = make_float4((float)((px[u][0] + F.shift[sl[u]][0]) - F.origin[0]),
-                                (float)((px[u][1] + F.shift[sl[u]][1]) - F.origin[1]),
-                                (float)((px[u][2] + F.shift[sl[u]][2]) - F.origin[2]), aq[u].y);
-            SB[k] = make_float4((float)(pv[u][0] - vref[0]), (float)(pv[u][1] - vref[1]),
-                                (float)(pv[u][2] - vref[2]), (sk[u] & 1) ? -aq[u].x : aq[u].x);
-            SC[k] = make_float4((float)pw[u][0], (float)pw[u][1], (float)pw[u][2], aq[u].w);
-        }
-    }
+    stage_force(s, F, M, vref, SA, SB, SC);
     __syncthreads();
     if (!has_cell) return;
     const uint32_t nt = F.off[tslot + 1] - F.off[tslot];
@@ -1089,7 +1109,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_force_brick(DevState s)
         };
         const bool replay = masks_fit(F, ts, G);
         const uint64_t *recp = (replay && fluid) ? s.masks + (size_t)p * kMaskSlots + g : nullptr;
-        stencil_windows(F, F.win[w], ts, lane, target ? g : 0, G, false, replay,
+        stencil_windows(F, win[w], ts, lane, target ? g : 0, G, false, replay,
                         const_cast<uint64_t *>(recp),
             [&](uint32_t k, bool in_row) {
                 const float4 c = SA[k];
@@ -1101,6 +1121,367 @@ __global__ void __launch_bounds__(kBrickThreads) k_force_brick(DevState s)
                 pair(SA[k], SB[k], SC[k], f, n);
                 accum(f, n);
             });
+        const double f0 = group_total(F0.s, KAHAN ? F0.c : 0.0f, lane, ntc, G);
+        const double f1 = group_total(F1.s, KAHAN ? F1.c : 0.0f, lane, ntc, G);
+        const double f2 = group_total(F2.s, KAHAN ? F2.c : 0.0f, lane, ntc, G);
+        const double t0 = group_total(T0.s, KAHAN ? T0.c : 0.0f, lane, ntc, G);
+        const double t1 = group_total(T1.s, KAHAN ? T1.c : 0.0f, lane, ntc, G);
+        const double t2 = group_total(T2.s, KAHAN ? T2.c : 0.0f, lane, ntc, G);
+        if (target && g == 0) {
+            const double FF[3] = {fluid ? f0 : 0.0, fluid ? f1 : 0.0, fluid ? f2 : 0.0};
+            const double TT[3] = {fluid ? t0 : 0.0, fluid ? t1 : 0.0, fluid ? t2 : 0.0};
+            err |= force_finish<float>(s, d, p, I.sp, FF, TT);
+        }
+    }
+    if (err) atomicOr(s.err, err);
+}
+
+// ------------------------------------------------------ candidate-major brick sweeps ---
+// Same bricks, staging and fallbacks as above, with the neighbour test turned around.  The
+// wave of a target cell lays the candidates of its 27-cell stencil (nine rows of three
+// x-adjacent cells, each a contiguous run of the staged particles) out as one list, held
+// in registers as windows of 64 candidates, one per lane.  Testing one target against a
+// window is then one 64-lane comparison whose ballot is the window's hit mask, so targets
+// are tested one after another with every lane busy.  The density sweep stores the masks
+// (one word per window and target) and the force sweep replays them.  Pair terms are
+// evaluated with lanes = (target, group g of G): group g takes the g-th of G equal
+// consecutive shares of the target's hits in list order.
+
+constexpr int kCandWin = 10;      // windows per wave: stencils of up to 640 candidates
+constexpr int kListTargets = 32;  // targets per round of the density sweep (masks in LDS)
+static_assert(kCandWin <= kMaskSlots, "a target's masks must fit its mask slots");
+static_assert(kStageDensity <= 32767 && kStageForce <= 32767, "staged indices are int16");
+
+// The nine stencil rows of a target cell as one list: writes the staged index of every
+// list position below kCandWin * 64 into the wave's table (row by row, lanes along the
+// row) and returns the list length, its windows of 64 and the offset from list position
+// to staged index in row 4, whose middle cell is the target's own.
+struct StencilList {
+    uint32_t C, NW;
+    int32_t self_off;
+};
+
+__device__ __forceinline__ StencilList stencil_list(const BrickFrame &F, const int ts[3], int lane,
+                                                    int16_t *tbl)
+{
+    StencilList S;
+    uint32_t acc = 0;
+    S.self_off = 0;
+#pragma unroll
+    for (int r = 0; r < 9; r++) {
+        const int s0 = slot_index(ts[0] - 1, ts[1] - 1 + r % 3, ts[2] - 1 + r / 3);
+        const uint32_t b = __builtin_amdgcn_readfirstlane(F.off[s0]);
+        const uint32_t e = __builtin_amdgcn_readfirstlane(F.off[s0 + 3]);
+        if (r == 4) S.self_off = (int32_t)b - (int32_t)acc;
+        for (uint32_t i = (uint32_t)lane; i < e - b && acc + i < (uint32_t)(kCandWin * 64); i += 64)
+            tbl[acc + i] = (int16_t)(b + i);
+        acc += e - b;
+    }
+    S.C = acc;
+    S.NW = (acc + 63) / 64;
+    __builtin_amdgcn_wave_barrier();
+    return S;
+}
+
+// List position of the target with staged index kt.
+__device__ __forceinline__ uint32_t stencil_self(const StencilList &S, uint32_t kt)
+{
+    return (uint32_t)((int32_t)kt - S.self_off);
+}
+
+// Workgroups are dealt to the XCDs in turn (workgroup i runs on XCD i mod kXcd).  Giving
+// each XCD runs of kXcdRun consecutive bricks of the Morton order makes the neighbourhoods
+// that its resident workgroups stage overlap, so more staging loads hit that XCD's own L2,
+// while the runs stay short enough to spread uneven work over all XCDs.
+constexpr uint32_t kXcd = 8, kXcdRun = 16;
+__device__ __forceinline__ uint32_t brick_of_workgroup(uint32_t wg, uint32_t nb)
+{
+    const uint32_t P = kXcd * kXcdRun, base = wg / P * P, T = min(P, nb - base), in = wg - base;
+    const uint32_t q = T / kXcd, r = T % kXcd, x = in % kXcd;
+    return base + x * q + min(x, r) + in / kXcd;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
+    return v;
+}
+
+// Share g of G of a target's H hits (mask words word(0..)): hits [H g / G, H (g+1) / G) in
+// list order.  Returns their count, the window c of the first and the bits of that window
+// from the first on.
+template <class Word>
+__device__ __forceinline__ void hit_share(Word &&word, uint32_t H, int g, int G, uint32_t &cnt,
+                                          int &c, uint64_t &mc)
+{
+    const uint32_t lo = (H * (uint32_t)g) / (uint32_t)G;
+    cnt = (H * (uint32_t)(g + 1)) / (uint32_t)G - lo;
+    c = 0;
+    mc = 0;
+    if (cnt == 0) return;
+    uint32_t skip = lo;
+    mc = word(0);
+    uint32_t pc = (uint32_t)__popcll(mc);
+    while (skip >= pc) {
+        skip -= pc;
+        mc = word(++c);
+        pc = (uint32_t)__popcll(mc);
+    }
+    for (; skip; skip--) mc &= mc - 1;
+}
+
+__device__ __forceinline__ float kernel_W_fast(int kernel, float r2, float inv_h, float wnorm)
+{
+    const float q = fast_sqrt(r2) * inv_h;
+    if (kernel == KERNEL_WENDLAND) {
+        const float t = 1.0f - 0.5f * q;
+        const float t2 = t * t;
+        return wnorm * t2 * t2 * (2.0f * q + 1.0f);
+    }
+    if (q < 1.0f) return wnorm * (1.0f - 1.5f * q * q + 0.75f * q * q * q);
+    const float t = 2.0f - q;
+    return wnorm * 0.25f * t * t * t;
+}
+
+template <bool KAHAN>
+__global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
+{
+    __shared__ BrickFrame F;
+    __shared__ float4 stage[kStageDensity];
+    __shared__ int16_t tbl[kBrickThreads / 64][kCandWin][64];
+    __shared__ uint64_t msk[kBrickThreads / 64][kListTargets][kCandWin];
+    const uint32_t brick = brick_of_workgroup(blockIdx.x, gridDim.x);
+    const uint32_t bxyz = s.brick_xyz[brick];
+    const InstDesc *d = s.desc + s.brick_inst[brick];
+    const uint8_t *SK = s.sk[s.cur];
+    const uint32_t M = brick_frame(s, d, bxyz, F, kStageDensity);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int ts[3];
+    const bool has_cell = brick_target(d, bxyz, w, ts);
+    const int tslot = slot_index(ts[0], ts[1], ts[2]);
+    uint32_t err = 0;
+    if (!F.ok) {
+        if (has_cell) {
+            const uint32_t nt = F.off[tslot + 1] - F.off[tslot];
+            for (uint32_t i = lane; i < nt; i += 64) err |= density_one<float, KAHAN>(s, d, F.begin[tslot] + i);
+        }
+        if (err) atomicOr(s.err, err);
+        return;
+    }
+    stage_density(s, F, M, stage);
+    __syncthreads();
+    if (!has_cell) return;
+    const uint32_t toff = __builtin_amdgcn_readfirstlane(F.off[tslot]);
+    const uint32_t pbase = __builtin_amdgcn_readfirstlane(F.begin[tslot]);
+    const uint32_t nt = __builtin_amdgcn_readfirstlane(F.off[tslot + 1]) - toff;
+    if (nt == 0) return;
+    const StencilList S = stencil_list(F, ts, lane, &tbl[w][0][0]);
+    if (S.NW > (uint32_t)kCandWin) {
+        for (uint32_t i = lane; i < nt; i += 64) err |= density_one<float, KAHAN>(s, d, pbase + i);
+        if (err) atomicOr(s.err, err);
+        return;
+    }
+    float cx[kCandWin], cy[kCandWin], cz[kCandWin];
+#pragma unroll
+    for (int c = 0; c < kCandWin; c++) {
+        cx[c] = cy[c] = cz[c] = __builtin_inff();  // never within reach
+        if (c < (int)S.NW && 64u * (uint32_t)c + (uint32_t)lane < S.C) {
+            const float4 q = stage[tbl[w][c][lane]];
+            cx[c] = q.x;
+            cy[c] = q.y;
+            cz[c] = q.z;
+        }
+    }
+    const float cut2 = (float)d->cut2, inv_h = (float)d->inv_h, wnorm = (float)d->wnorm;
+    const int kernel = d->kernel;
+    for (uint32_t t0 = 0; t0 < nt; t0 += kListTargets) {
+        const uint32_t ntc = min((uint32_t)kListTargets, nt - t0);
+        // test: one target at a time against every window; lane t collects target t's masks
+        uint32_t mlo[kCandWin], mhi[kCandWin];
+#pragma unroll
+        for (int c = 0; c < kCandWin; c++) mlo[c] = mhi[c] = 0u;
+        for (uint32_t t = 0; t < ntc; t++) {
+            const uint32_t kt = toff + t0 + t;
+            const float4 T = stage[kt];
+            const uint32_t vs = stencil_self(S, kt);
+            const bool mine = (uint32_t)lane == t;
+#pragma unroll
+            for (int c = 0; c < kCandWin; c++) {
+                if (c < (int)S.NW) {
+                    const float d0 = cx[c] - T.x, d1 = cy[c] - T.y, d2 = cz[c] - T.z;
+                    uint64_t m = __ballot(d0 * d0 + d1 * d1 + d2 * d2 < cut2);
+                    if ((vs >> 6) == (uint32_t)c) m &= ~(1ull << (vs & 63));
+                    mlo[c] = mine ? (uint32_t)m : mlo[c];
+                    mhi[c] = mine ? (uint32_t)(m >> 32) : mhi[c];
+                }
+            }
+        }
+        if ((uint32_t)lane < ntc) {
+            uint64_t *gm = s.masks + (size_t)(pbase + t0 + lane) * kMaskSlots;
+#pragma unroll
+            for (int c = 0; c < kCandWin; c++) {
+                if (c < (int)S.NW) {
+                    const uint64_t m = ((uint64_t)mhi[c] << 32) | mlo[c];
+                    msk[w][lane][c] = m;
+                    gm[c] = m;
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        // kernel sums: lanes (target tt, group g)
+        const int G = 64 / (int)ntc;
+        const int g = lane / (int)ntc, tt = lane % (int)ntc;
+        const bool act = g < G;
+        const uint64_t *mrow = msk[w][tt];
+        uint32_t H = 0;
+        for (int c = 0; c < (int)S.NW; c++) H += (uint32_t)__popcll(mrow[c]);
+        uint32_t cnt;
+        int c;
+        uint64_t mc;
+        hit_share([&](int cc) { return mrow[cc]; }, act ? H : 0u, g, G, cnt, c, mc);
+        const uint32_t most = wave_max(cnt);
+        const float4 me = stage[toff + t0 + tt];
+        Acc<float, KAHAN> sw, su;
+        for (uint32_t i = 0; i < most; i++) {
+            if (i < cnt) {
+                while (mc == 0) mc = mrow[++c];
+                const int j = __builtin_ctzll(mc);
+                mc &= mc - 1;
+                const float4 q = stage[tbl[w][c][j]];
+                const float d0 = me.x - q.x, d1 = me.y - q.y, d2 = me.z - q.z;
+                const float W = kernel_W_fast(kernel, d0 * d0 + d1 * d1 + d2 * d2, inv_h, wnorm);
+                sw.add(W);
+                su.add(q.w != me.w ? W : 0.0f);
+            }
+        }
+        const double SW = group_total(sw.s, KAHAN ? sw.c : 0.0f, lane, (int)ntc, G);
+        const double SU = group_total(su.s, KAHAN ? su.c : 0.0f, lane, (int)ntc, G);
+        if (act && g == 0) {
+            const uint32_t p = pbase + t0 + tt;
+            const uint8_t ski = SK[p];
+            err |= density_finish<float>(s, d, p, ski & 1, ski >> 1, SW, SU);
+        }
+        __builtin_amdgcn_wave_barrier();  // the masks are rewritten by the next round
+    }
+    if (err) atomicOr(s.err, err);
+}
+
+template <bool KAHAN>
+__global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
+{
+    __shared__ BrickFrame F;
+    __shared__ float4 SA[kStageForce];   // position (brick frame), P/rho^2
+    __shared__ float4 SB[kStageForce];   // velocity - v_ref, V (negative: viscous species)
+    __shared__ float4 SC[kStageForce];   // spin, V/S
+    __shared__ double vref[3];
+    __shared__ int16_t tbl[kBrickThreads / 64][kCandWin][64];
+    const uint32_t brick = brick_of_workgroup(blockIdx.x, gridDim.x);
+    const uint32_t bxyz = s.brick_xyz[brick];
+    const InstDesc *d = s.desc + s.brick_inst[brick];
+    const uint8_t *SK = s.sk[s.cur];
+    const uint32_t M = brick_frame(s, d, bxyz, F, kStageForce, s.v[s.cur], vref);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int ts[3];
+    const bool has_cell = brick_target(d, bxyz, w, ts);
+    const int tslot = slot_index(ts[0], ts[1], ts[2]);
+    uint32_t err = 0;
+    if (!F.ok) {
+        if (has_cell) {
+            const uint32_t nt = F.off[tslot + 1] - F.off[tslot];
+            for (uint32_t i = lane; i < nt; i += 64) err |= force_one<float, KAHAN>(s, d, F.begin[tslot] + i);
+        }
+        if (err) atomicOr(s.err, err);
+        return;
+    }
+    stage_force(s, F, M, vref, SA, SB, SC);
+    __syncthreads();
+    if (!has_cell) return;
+    const uint32_t toff = F.off[tslot], pbase = F.begin[tslot];
+    const uint32_t nt = F.off[tslot + 1] - toff;
+    if (nt == 0) return;
+    const StencilList S = stencil_list(F, ts, lane, &tbl[w][0][0]);
+    if (S.NW > (uint32_t)kCandWin) {
+        for (uint32_t i = lane; i < nt; i += 64) err |= force_one<float, KAHAN>(s, d, pbase + i);
+        if (err) atomicOr(s.err, err);
+        return;
+    }
+    const ForceK<float> K(d);
+    const float im2_0 = (float)(1.0 / (d->mass[0] * d->mass[0]));
+    const float im2_1 = (float)(1.0 / (d->mass[1] * d->mass[1]));
+    const int NW = (int)S.NW;
+    for (uint32_t chunk = 0; chunk < nt; chunk += 64) {
+        const int ntc = (int)min(64u, nt - chunk);
+        const int G = 64 / ntc;
+        const int g = lane / ntc, tt = lane % ntc;
+        const bool target = g < G;
+        const uint32_t p = pbase + chunk + tt;
+        const bool fluid = target && (SK[p] >> 1) == KIND_FLUID;
+        const uint32_t ki = toff + chunk + tt;
+        const float4 Ai = SA[ki], Bi = SB[ki], Ci = SC[ki];
+        ForceP<float> I;
+        I.sp = Bi.w < 0.0f ? 1 : 0;
+        I.m = I.sp ? K.m1 : K.m0;
+        I.V = fabsf(Bi.w);
+        I.Pr = Ai.w;
+        I.ir2 = I.V * I.V * (I.sp ? im2_1 : im2_0);
+        I.VS = Ci.w;
+        // all of the target's mask words at once (no chain of dependent loads); group g
+        // takes hits [lo, lo + cnt), starting in window c
+        const uint64_t *gm = s.masks + (size_t)p * kMaskSlots;
+        uint64_t mw[kCandWin];
+        uint32_t H = 0;
+#pragma unroll
+        for (int cc = 0; cc < kCandWin; cc++) {
+            mw[cc] = (fluid && cc < NW) ? gm[cc] : 0ull;
+            H += (uint32_t)__popcll(mw[cc]);
+        }
+        const uint32_t lo = (H * (uint32_t)g) / (uint32_t)G;
+        const uint32_t cnt = (H * (uint32_t)(g + 1)) / (uint32_t)G - lo;
+        int c = 0;
+        uint32_t pre = 0, before = 0;
+#pragma unroll
+        for (int cc = 0; cc < kCandWin; cc++) {
+            pre += (uint32_t)__popcll(mw[cc]);
+            if (pre <= lo) {
+                c = cc + 1;
+                before = pre;
+            }
+        }
+        uint64_t mc = 0, nxt = 0;  // bits of window c still to walk; window c + 1
+#pragma unroll
+        for (int cc = 0; cc < kCandWin; cc++) {
+            if (cc == c) mc = mw[cc];
+            if (cc == c + 1) nxt = mw[cc];
+        }
+        for (uint32_t k = lo - before; k; k--) mc &= mc - 1;
+        const uint32_t most = wave_max(cnt);
+        Acc<float, KAHAN> F0, F1, F2, T0, T1, T2;
+        for (uint32_t i = 0; i < most; i++) {
+            if (i < cnt) {
+                while (mc == 0) {
+                    mc = nxt;
+                    ++c;
+                    nxt = c + 1 < NW ? gm[c + 1] : 0ull;
+                }
+                const int j = __builtin_ctzll(mc);
+                mc &= mc - 1;
+                const uint32_t k = (uint32_t)tbl[w][c][j];
+                const float4 A = SA[k], B = SB[k], C = SC[k];
+                ForceP<float> J;
+                J.sp = B.w < 0.0f ? 1 : 0;
+                J.m = J.sp ? K.m1 : K.m0;
+                J.V = fabsf(B.w);
+                J.Pr = A.w;
+                J.ir2 = J.V * J.V * (J.sp ? im2_1 : im2_0);
+                J.VS = C.w;
+                float f[3], n[3];
+                pair_force_f32(K, I, J, Ai.x - A.x, Ai.y - A.y, Ai.z - A.z, Bi.x - B.x, Bi.y - B.y,
+                               Bi.z - B.z, 0.5f * (Ci.x + C.x), 0.5f * (Ci.y + C.y),
+                               0.5f * (Ci.z + C.z), f, n);
+                F0.add(f[0]); F1.add(f[1]); F2.add(f[2]);
+                T0.add(n[0]); T1.add(n[1]); T2.add(n[2]);
+            }
+        }
         const double f0 = group_total(F0.s, KAHAN ? F0.c : 0.0f, lane, ntc, G);
         const double f1 = group_total(F1.s, KAHAN ? F1.c : 0.0f, lane, ntc, G);
         const double f2 = group_total(F2.s, KAHAN ? F2.c : 0.0f, lane, ntc, G);
@@ -1358,6 +1739,7 @@ hipError_t launch_density(const DevState &d, const Launch &L, hipStream_t st)
     unsigned g = grid_for(d.n_waves, L.bs_density);
     if (d.precision == 0) k_density<double, false><<<g, L.bs_density, 0, st>>>(d);
     else if (L.sweep == SWEEP_BRICK && d.n_bricks) k_density_brick<true><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
+    else if (L.sweep == SWEEP_CAND && d.n_bricks) k_density_cand<true><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
     else k_density<float, true><<<g, L.bs_density, 0, st>>>(d);
     return hipGetLastError();
 }
@@ -1367,6 +1749,7 @@ hipError_t launch_force(const DevState &d, const Launch &L, hipStream_t st)
     unsigned g = grid_for(d.n_waves, L.bs_force);
     if (d.precision == 0) k_force<double, false><<<g, L.bs_force, 0, st>>>(d);
     else if (L.sweep == SWEEP_BRICK && d.n_bricks) k_force_brick<true><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
+    else if (L.sweep == SWEEP_CAND && d.n_bricks) k_force_cand<true><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
     else k_force<float, true><<<g, L.bs_force, 0, st>>>(d);
     return hipGetLastError();
 }

@@ -691,7 +691,7 @@ sph_status sph_batch_set_tuning(sph_batch *b, const sph_tuning *t)
             return SPH_E_INVALID;
         }
     if (t->use_graph < -1 || t->use_graph > 1) { b->err = "use_graph must be -1, 0 or 1"; return SPH_E_INVALID; }
-    if (t->sweep < 0 || t->sweep > 2) { b->err = "sweep must be 0, 1 or 2"; return SPH_E_INVALID; }
+    if (t->sweep < 0 || t->sweep > 3) { b->err = "sweep must be 0, 1, 2 or 3"; return SPH_E_INVALID; }
     if (t->sweep) b->L.sweep = t->sweep;
     if (t->block_density) b->L.bs_density = t->block_density;
     if (t->block_force) b->L.bs_force = t->block_force;

@@ -76,11 +76,11 @@ constexpr int kMaskSlots = 16;
 
 // Sweep implementations: one thread per particle walking its own cell stencil, or one
 // workgroup per 2x2x2-cell brick with the brick's neighbourhood staged in LDS.
-enum { SWEEP_THREAD = 1, SWEEP_BRICK = 2 };
+enum { SWEEP_THREAD = 1, SWEEP_BRICK = 2, SWEEP_CAND = 3 };
 
 struct Launch {
     int bs_density = 256, bs_force = 256, bs_stream = 256;
-    int sweep = SWEEP_BRICK;  // used when every instance allows it (FP32-mixed, cf = 1)
+    int sweep = SWEEP_CAND;  // brick sweeps when every instance allows them (FP32-mixed, cf = 1)
 };
 
 // Launchers (kernels.hip).  All enqueue on `st` and return hipGetLastError().

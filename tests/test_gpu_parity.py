@@ -264,14 +264,16 @@ def test_step_before_init_is_a_state_error():
     s.close()
 
 
+@pytest.mark.parametrize("sweep", [2, 3])
 @pytest.mark.parametrize("case", ["cylinder", "box4096", "jitter"])
-def test_brick_sweep_matches_thread_sweep(case):
-    """The LDS-staged brick sweeps and the per-particle sweeps compute the same FP32-mixed
-    fields up to single-precision rounding."""
+def test_brick_sweep_matches_thread_sweep(case, sweep):
+    """The LDS-staged brick sweeps (target-major and candidate-major) and the per-particle
+    sweeps compute the same FP32-mixed fields up to single-precision rounding."""
     w = CELL_CASES[case]()
-    a = _sim(w, MIXED, sweep=2)
+    print(f"[brick] {case} sweep={sweep} n={w.n}", flush=True)
+    a = _sim(w, MIXED, sweep=sweep)
     b = _sim(w, MIXED, sweep=1)
-    assert a.get_tuning()["sweep"] == 2 and b.get_tuning()["sweep"] == 1
+    assert a.get_tuning()["sweep"] == sweep and b.get_tuning()["sweep"] == 1
     a.step(1e-4, w.Omega, 5)
     b.step(1e-4, w.Omega, 5)
     oa, ob = a.read(), b.read()
@@ -284,15 +286,41 @@ def test_brick_sweep_matches_thread_sweep(case):
     b.close()
 
 
+@pytest.mark.parametrize("sweep", [2, 3])
 @pytest.mark.parametrize("h_factor", [1.6, 2.2])
-def test_brick_fallback_when_cells_are_full(h_factor):
+def test_brick_fallback_when_cells_are_full(h_factor, sweep):
     """Neighbourhoods too large to stage fall back to the per-particle code path."""
     w = I.make_box(20, kernel=I.KERNEL_WENDLAND_C2, h_factor=h_factor)
+    print(f"[fallback] h/dx={h_factor} sweep={sweep} n={w.n}", flush=True)
     ref = O.State.from_workload(w)
-    s = _sim(w, MIXED, sweep=2)
+    s = _sim(w, MIXED, sweep=sweep)
     e = field_errors(s.read(), ref, w)
     print("fallback", h_factor, e, flush=True)
     for k in ("rho", "P", "acc", "alpha"):
+        assert e[k] < 1e-5, (k, e[k])
+    s.close()
+
+
+@pytest.mark.parametrize("n", [19, 23])
+def test_candidate_sweep_falls_back_for_long_stencils(n):
+    """Boxes whose 27-cell stencils reach 729 candidates (more than the 640 a wave holds):
+    those waves take the per-particle path, the rest of the brick the candidate-major one
+    (n = 23 also has bricks that fit the density sweep's LDS but not the force sweep's);
+    all match the oracle, initially and after a step."""
+    w = _jitter_box(n, seed=n, amp=0.05, h_factor=1.3)
+    print(f"[cand fallback] box n={n} particles={w.n}", flush=True)
+    ref = O.State.from_workload(w)
+    s = _sim(w, MIXED, sweep=3)
+    e = field_errors(s.read(), ref, w)
+    print("initial", e, flush=True)
+    for k in ("rho", "P", "acc", "alpha"):
+        assert e[k] < 1e-5, (k, e[k])
+    ref.step(1e-4, w.Omega, 1)
+    s.step(1e-4, w.Omega, 1)
+    e = field_errors(s.read(), ref, w)
+    print("one step", e, flush=True)
+    assert positions_ok(e, 1e-5, 1), e
+    for k in ("v", "omega", "rho", "P"):
         assert e[k] < 1e-5, (k, e[k])
     s.close()
 
