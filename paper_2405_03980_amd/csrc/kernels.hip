@@ -659,11 +659,11 @@ typedef int16_t WindowTable[kBrickThreads / 64][kMergeWin][64];
 __device__ __forceinline__ int slot_index(int x, int y, int z) { return x + 4 * (y + 4 * z); }
 
 // Fills the frame (wave 0: one lane per slot, a wave-level scan for the offsets) and
-// returns the staged particle count.  With Vv, the lane of slot (1,1,1), the brick's
+// returns the staged particle count; F.ok tells whether they fit stage_max.  With Vv, the lane of slot (1,1,1), the brick's
 // first cell, also loads the velocity of that cell's first particle into vref.
 __device__ __forceinline__ uint32_t brick_frame(const DevState &s, const InstDesc *d, uint32_t bxyz,
-                                                BrickFrame &F, int stage_max,
-                                                const double *Vv = nullptr, double *vref = nullptr)
+                                            BrickFrame &F, int stage_max,
+                                            const double *Vv = nullptr, double *vref = nullptr)
 {
     const int t = threadIdx.x;
     const int b[3] = {(int)(bxyz & 1023), (int)((bxyz >> 10) & 1023), (int)(bxyz >> 20)};
@@ -733,57 +733,76 @@ __device__ __forceinline__ bool brick_target(const InstDesc *d, uint32_t bxyz, i
 }
 
 
-// Sum of the G partial (Kahan) sums of a target, held by lanes t, t + ntc, ...
+// Sum of the G partial (Kahan) sums of a target, held by lanes t, t + ntc, ... (t < ntc):
+// a tree over the groups in a fixed order, in FP64; the total is valid on lane t.
 __device__ __forceinline__ double group_total(float s_, float c_, int lane, int ntc, int G)
 {
-    double tot = 0.0;
-    for (int g = 0; g < G; g++) {
-        int src = lane + g * ntc;
-        float a = __shfl(s_, src < 64 ? src : lane);
-        float b = __shfl(c_, src < 64 ? src : lane);
-        tot += (double)a - (double)b;
+    double v = (double)s_ - (double)c_;
+    const int g = lane / ntc;
+    for (int off = 1; off < G; off <<= 1) {
+        const int src = lane + off * ntc;
+        const double o = __shfl(v, src < 64 ? src : lane);
+        if ((g & (2 * off - 1)) == 0 && g + off < G) v += o;
     }
-    return tot;
+    return v;
 }
 
-// Stages the positions of the brick's M neighbourhood particles relative to the brick
-// centre (FP64 difference, then FP32) and their species: each thread takes up to two
-// particles and issues all their loads first.
-__device__ __forceinline__ void stage_density(const DevState &s, const BrickFrame &F, uint32_t M,
-                                              float4 *stage)
+// Clears the k lowest set bits of m (k < popcount(m)): a binary search for the position of
+// set bit k, halving the span six times.
+__device__ __forceinline__ uint64_t drop_low_bits(uint64_t m, uint32_t k)
+{
+    uint32_t pos = 0;
+    for (uint32_t w = 32; w >= 1; w >>= 1) {
+        const uint32_t n = (uint32_t)__popcll((m >> pos) & ((1ull << w) - 1ull));
+        if (n <= k) {
+            k -= n;
+            pos += w;
+        }
+    }
+    return m & ~((1ull << pos) - 1ull);
+}
+
+// Density staging walks the 64 slots of the neighbourhood with kSlotThreads threads each:
+// thread `sub` of a slot takes its particles sub, sub + kSlotThreads, ..., two at a time
+// so that their loads are in flight together.
+constexpr int kSlotThreads = kBrickThreads / 64;
+static_assert(kSlotThreads * 64 == kBrickThreads, "staging assigns whole slots to threads");
+
+// Stages the positions of the brick's neighbourhood particles relative to the brick centre
+// (FP64 difference, then FP32) and their species.
+__device__ __forceinline__ void stage_density(const DevState &s, const BrickFrame &F, float4 *stage)
 {
     const uint32_t N = s.N;
     const double *X = s.x[s.cur];
     const uint8_t *SK = s.sk[s.cur];
-    for (uint32_t k0 = threadIdx.x; k0 < M; k0 += 2 * kBrickThreads) {
-        uint32_t kk[2], qq[2];
-        int sl[2];
-        for (int u = 0; u < 2; u++) {
-            kk[u] = k0 + (uint32_t)u * kBrickThreads;
-            sl[u] = slot_of(F, min(kk[u], M - 1));
-            qq[u] = F.begin[sl[u]] + (min(kk[u], M - 1) - F.off[sl[u]]);
-        }
+    const int sl = (int)threadIdx.x / kSlotThreads;
+    const uint32_t sub = threadIdx.x % kSlotThreads;
+    const uint32_t off = F.off[sl], cnt = F.off[sl + 1] - off, beg = F.begin[sl];
+    for (uint32_t k0 = sub; k0 < cnt; k0 += 2 * kSlotThreads) {
         double px[2][3];
         uint8_t sk[2];
         for (int u = 0; u < 2; u++) {
-            for (int a = 0; a < 3; a++) px[u][a] = X[(size_t)a * N + qq[u]];
-            sk[u] = SK[qq[u]];
+            const uint32_t q = beg + min(k0 + (uint32_t)(u * kSlotThreads), cnt - 1);
+            for (int a = 0; a < 3; a++) px[u][a] = X[(size_t)a * N + q];
+            sk[u] = SK[q];
         }
         for (int u = 0; u < 2; u++) {
-            if (kk[u] >= M) break;
+            const uint32_t k = k0 + (uint32_t)(u * kSlotThreads);
+            if (k >= cnt) break;
             float4 v;
-            v.x = (float)((px[u][0] + F.shift[sl[u]][0]) - F.origin[0]);
-            v.y = (float)((px[u][1] + F.shift[sl[u]][1]) - F.origin[1]);
-            v.z = (float)((px[u][2] + F.shift[sl[u]][2]) - F.origin[2]);
+            v.x = (float)((px[u][0] + F.shift[sl][0]) - F.origin[0]);
+            v.y = (float)((px[u][1] + F.shift[sl][1]) - F.origin[1]);
+            v.z = (float)((px[u][2] + F.shift[sl][2]) - F.origin[2]);
             v.w = (float)(sk[u] & 1);
-            stage[kk[u]] = v;
+            stage[off + k] = v;
         }
     }
 }
 
 // Stages what the force sweep reads of the brick's M neighbourhood particles: position
 // relative to the brick centre and P/rho^2; velocity relative to vref and V (negative for
-// the viscous species); spin and V/S.  Each thread takes up to three particles.
+// the viscous species); spin and V/S.  Each thread takes up to three particles spread
+// evenly over the neighbourhood (the heavier force staging prefers this to whole slots).
 __device__ __forceinline__ void stage_force(const DevState &s, const BrickFrame &F, uint32_t M,
                                             const double *vref, float4 *SA, float4 *SB, float4 *SC)
 {
@@ -973,7 +992,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_brick(DevState s)
     const uint32_t bxyz = s.brick_xyz[blockIdx.x];
     const InstDesc *d = s.desc + s.brick_inst[blockIdx.x];
     const uint8_t *SK = s.sk[s.cur];
-    const uint32_t M = brick_frame(s, d, bxyz, F, kStageDensity);
+    brick_frame(s, d, bxyz, F, kStageDensity);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int ts[3];
     const bool has_cell = brick_target(d, bxyz, w, ts);
@@ -987,7 +1006,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_brick(DevState s)
         if (err) atomicOr(s.err, err);
         return;
     }
-    stage_density(s, F, M, stage);
+    stage_density(s, F, stage);
     __syncthreads();
     if (!has_cell) return;
     const uint32_t nt = F.off[tslot + 1] - F.off[tslot];
@@ -1227,7 +1246,7 @@ __device__ __forceinline__ void hit_share(Word &&word, uint32_t H, int g, int G,
         mc = word(++c);
         pc = (uint32_t)__popcll(mc);
     }
-    for (; skip; skip--) mc &= mc - 1;
+    mc = drop_low_bits(mc, skip);
 }
 
 __device__ __forceinline__ float kernel_W_fast(int kernel, float r2, float inv_h, float wnorm)
@@ -1254,7 +1273,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
     const uint32_t bxyz = s.brick_xyz[brick];
     const InstDesc *d = s.desc + s.brick_inst[brick];
     const uint8_t *SK = s.sk[s.cur];
-    const uint32_t M = brick_frame(s, d, bxyz, F, kStageDensity);
+    brick_frame(s, d, bxyz, F, kStageDensity);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int ts[3];
     const bool has_cell = brick_target(d, bxyz, w, ts);
@@ -1268,7 +1287,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
         if (err) atomicOr(s.err, err);
         return;
     }
-    stage_density(s, F, M, stage);
+    stage_density(s, F, stage);
     __syncthreads();
     if (!has_cell) return;
     const uint32_t toff = __builtin_amdgcn_readfirstlane(F.off[tslot]);
@@ -1453,7 +1472,7 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
             if (cc == c) mc = mw[cc];
             if (cc == c + 1) nxt = mw[cc];
         }
-        for (uint32_t k = lo - before; k; k--) mc &= mc - 1;
+        if (cnt) mc = drop_low_bits(mc, lo - before);
         const uint32_t most = wave_max(cnt);
         Acc<float, KAHAN> F0, F1, F2, T0, T1, T2;
         for (uint32_t i = 0; i < most; i++) {

@@ -27,6 +27,7 @@ from collections import defaultdict
 HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_MIB = 1024
 KERNEL_GROUPS = {"k_keys<float>": "keys", "k_scatter": "scatter", "k_reorder<float>": "reorder",
+                 "k_density_cand<true>": "density", "k_force_cand<true>": "force",
                  "k_density_brick<true>": "density", "k_force_brick<true>": "force"}
 
 
@@ -84,11 +85,11 @@ def summarize(root: str, out_json: str | None = None, workload: str = "") -> dic
         for kname, group in KERNEL_GROUPS.items():
             f = _avg(allc["fetch"], kname, "FETCH_SIZE")
             w = _avg(allc["write"], kname, "WRITE_SIZE")
-            if f is not None and w is not None:
+            if f is not None and w is not None and group not in kern:
                 kern[group] = {"kernel": kname, "FETCH_SIZE_KiB": f, "WRITE_SIZE_KiB": w}
         sq = {}
         for kname, group in KERNEL_GROUPS.items():
-            if kname in allc.get("sq", {}):
+            if kname in allc.get("sq", {}) and group not in sq:
                 sq[group] = {cn: sum(v) / len(v) for cn, v in allc["sq"][kname].items()}
         res = {"source_sha": source_sha(), "fetch_scale": kib / cf, "write_scale": kib / cw,
                "copy_MiB": COPY_MIB, "copy_FETCH_SIZE_KiB": cf, "copy_WRITE_SIZE_KiB": cw,
