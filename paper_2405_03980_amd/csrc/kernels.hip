@@ -801,8 +801,9 @@ __device__ __forceinline__ void stage_density(const DevState &s, const BrickFram
 
 // Stages what the force sweep reads of the brick's M neighbourhood particles: position
 // relative to the brick centre and P/rho^2; velocity relative to vref and V (negative for
-// the viscous species); spin and V/S.  Each thread takes up to three particles spread
-// evenly over the neighbourhood (the heavier force staging prefers this to whole slots).
+// the viscous species); half the spin (exact, so (w_i + w_j)/2 takes one add) and V/S.
+// Each thread takes up to three particles spread evenly over the neighbourhood (the
+// heavier force staging prefers this to whole slots).
 __device__ __forceinline__ void stage_force(const DevState &s, const BrickFrame &F, uint32_t M,
                                             const double *vref, float4 *SA, float4 *SB, float4 *SC)
 {
@@ -840,7 +841,8 @@ __device__ __forceinline__ void stage_force(const DevState &s, const BrickFrame 
                                 (float)((px[u][2] + F.shift[sl[u]][2]) - F.origin[2]), aq[u].y);
             SB[k] = make_float4((float)(pv[u][0] - vref[0]), (float)(pv[u][1] - vref[1]),
                                 (float)(pv[u][2] - vref[2]), (sk[u] & 1) ? -aq[u].x : aq[u].x);
-            SC[k] = make_float4((float)pw[u][0], (float)pw[u][1], (float)pw[u][2], aq[u].w);
+            SC[k] = make_float4((float)(0.5 * pw[u][0]), (float)(0.5 * pw[u][1]), (float)(0.5 * pw[u][2]),
+                                aq[u].w);
         }
     }
 }
@@ -953,22 +955,49 @@ __device__ __forceinline__ void kernel_WF_fast(int kernel, float r2, float inv_h
     }
 }
 
-// The same pair terms as pair_force, without branches on the species: unlike and
-// viscous-viscous factors are 0/1 multipliers.
-__device__ __forceinline__ void pair_force_f32(const ForceK<float> &k, const ForceP<float> &I,
-                                               const ForceP<float> &J, float r0, float r1, float r2,
-                                               float v0, float v1, float v2, float hs0, float hs1,
-                                               float hs2, float f[3], float n[3])
+// Target-side factors of the staged FP32 pair terms (constant over a target's neighbours).
+struct ForceI32 {
+    float m, Pr, ir2, VS;
+    float xs;  // 1 for the normal species, -1 for the viscous one: B.w * xs < 0 marks unlike
+    float ev;  // -4 eta V for the viscous species, 0 for the other
+};
+
+// Target-side factors from the target's own staged values (SA.w = P/rho^2, SB.w = V with the
+// sign of the species, SC.w = V/S).
+__device__ __forceinline__ ForceI32 force_target(const ForceK<float> &k, float4 A, float4 B,
+                                                 float4 C, float im2_0, float im2_1)
+{
+    ForceI32 I;
+    const bool sp = B.w < 0.0f;
+    const float V = fabsf(B.w);
+    I.m = sp ? k.m1 : k.m0;
+    I.Pr = A.w;
+    I.ir2 = V * V * (sp ? im2_1 : im2_0);
+    I.VS = C.w;
+    I.xs = sp ? -1.0f : 1.0f;
+    I.ev = sp ? -k.eta4 * V : 0.0f;
+    return I;
+}
+
+// The same pair terms as pair_force from the staged neighbour (A, B, C as in the staging),
+// without branches on the species: the unlike terms are selected, the viscous-viscous one
+// vanishes through ev and max(-B.w, 0) (= V_j for a viscous neighbour, else 0).
+__device__ __forceinline__ void pair_force_f32(const ForceK<float> &k, const ForceI32 &I, float im2_0,
+                                               float im2_1, float4 A, float4 B, float4 C, float r0,
+                                               float r1, float r2, float v0, float v1, float v2,
+                                               float hs0, float hs1, float hs2, float f[3], float n[3])
 {
     float W, Fk;
     kernel_WF_fast(k.kernel, r0 * r0 + r1 * r1 + r2 * r2, k.inv_h, k.wnorm, W, Fk);
-    const float unl = I.sp != J.sp ? 1.0f : 0.0f;
-    const float nn = (I.sp & J.sp) ? 1.0f : 0.0f;
-    const float mm = I.m * J.m;
-    const float gp = mm * (I.Pr + J.Pr) * Fk;
-    const float gT = -k.sigT * mm * (I.ir2 + J.ir2) * Fk * unl;
-    const float gm = -k.Cl * W * (I.VS + J.VS) * unl;
-    const float gv = -k.eta4 * I.V * J.V * Fk * nn;
+    const bool spj = B.w < 0.0f;
+    const bool unl = B.w * I.xs < 0.0f;
+    const float Vj = fabsf(B.w);
+    const float ir2j = Vj * Vj * (spj ? im2_1 : im2_0);
+    const float mFk = I.m * (spj ? k.m1 : k.m0) * Fk;
+    const float gp = mFk * (I.Pr + A.w);
+    const float gT = unl ? -k.sigT * mFk * (I.ir2 + ir2j) : 0.0f;
+    const float gm = unl ? -k.Cl * W * (I.VS + C.w) : 0.0f;
+    const float gv = I.ev * fmaxf(-B.w, 0.0f) * Fk;
     const float u0 = v0 - (hs1 * r2 - hs2 * r1);
     const float u1 = v1 - (hs2 * r0 - hs0 * r2);
     const float u2 = v2 - (hs0 * r1 - hs1 * r0);
@@ -1065,7 +1094,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_force_brick(DevState s)
     __shared__ WindowTable win;
     __shared__ float4 SA[kStageForce];   // position (brick frame), P/rho^2
     __shared__ float4 SB[kStageForce];   // velocity - v_ref, V (negative: viscous species)
-    __shared__ float4 SC[kStageForce];   // spin, V/S
+    __shared__ float4 SC[kStageForce];   // half the spin, V/S
     __shared__ double vref[3];
     const uint32_t bxyz = s.brick_xyz[blockIdx.x];
     const InstDesc *d = s.desc + s.brick_inst[blockIdx.x];
@@ -1102,25 +1131,12 @@ __global__ void __launch_bounds__(kBrickThreads) k_force_brick(DevState s)
         const bool fluid = target && (SK[p] >> 1) == KIND_FLUID;
         const uint32_t ki = target ? kself : F.off[tslot];
         const float4 Ai = SA[ki], Bi = SB[ki], Ci = SC[ki];
-        ForceP<float> I;
-        I.sp = Bi.w < 0.0f ? 1 : 0;
-        I.m = I.sp ? K.m1 : K.m0;
-        I.V = fabsf(Bi.w);
-        I.Pr = Ai.w;
-        I.ir2 = I.V * I.V * (I.sp ? im2_1 : im2_0);
-        I.VS = Ci.w;
+        const ForceI32 I = force_target(K, Ai, Bi, Ci, im2_0, im2_1);
+        const int spi = Bi.w < 0.0f ? 1 : 0;
         Acc<float, KAHAN> F0, F1, F2, T0, T1, T2;
         auto pair = [&](const float4 &A, const float4 &B, const float4 &C, float f[3], float n[3]) {
-            ForceP<float> J;
-            J.sp = B.w < 0.0f ? 1 : 0;
-            J.m = J.sp ? K.m1 : K.m0;
-            J.V = fabsf(B.w);
-            J.Pr = A.w;
-            J.ir2 = J.V * J.V * (J.sp ? im2_1 : im2_0);
-            J.VS = C.w;
-            pair_force_f32(K, I, J, Ai.x - A.x, Ai.y - A.y, Ai.z - A.z, Bi.x - B.x, Bi.y - B.y,
-                           Bi.z - B.z, 0.5f * (Ci.x + C.x), 0.5f * (Ci.y + C.y),
-                           0.5f * (Ci.z + C.z), f, n);
+            pair_force_f32(K, I, im2_0, im2_1, A, B, C, Ai.x - A.x, Ai.y - A.y, Ai.z - A.z,
+                           Bi.x - B.x, Bi.y - B.y, Bi.z - B.z, Ci.x + C.x, Ci.y + C.y, Ci.z + C.z, f, n);
         };
         auto accum = [&](const float f[3], const float n[3]) {
             F0.add(f[0]); F1.add(f[1]); F2.add(f[2]);
@@ -1149,7 +1165,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_force_brick(DevState s)
         if (target && g == 0) {
             const double FF[3] = {fluid ? f0 : 0.0, fluid ? f1 : 0.0, fluid ? f2 : 0.0};
             const double TT[3] = {fluid ? t0 : 0.0, fluid ? t1 : 0.0, fluid ? t2 : 0.0};
-            err |= force_finish<float>(s, d, p, I.sp, FF, TT);
+            err |= force_finish<float>(s, d, p, spi, FF, TT);
         }
     }
     if (err) atomicOr(s.err, err);
@@ -1218,12 +1234,6 @@ __device__ __forceinline__ uint32_t brick_of_workgroup(uint32_t wg, uint32_t nb)
     const uint32_t P = kXcd * kXcdRun, base = wg / P * P, T = min(P, nb - base), in = wg - base;
     const uint32_t q = T / kXcd, r = T % kXcd, x = in % kXcd;
     return base + x * q + min(x, r) + in / kXcd;
-}
-
-__device__ __forceinline__ uint32_t wave_max(uint32_t v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
-    return v;
 }
 
 // Share g of G of a target's H hits (mask words word(0..)): hits [H g / G, H (g+1) / G) in
@@ -1358,20 +1368,20 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
         int c;
         uint64_t mc;
         hit_share([&](int cc) { return mrow[cc]; }, act ? H : 0u, g, G, cnt, c, mc);
-        const uint32_t most = wave_max(cnt);
         const float4 me = stage[toff + t0 + tt];
         Acc<float, KAHAN> sw, su;
-        for (uint32_t i = 0; i < most; i++) {
-            if (i < cnt) {
-                while (mc == 0) mc = mrow[++c];
-                const int j = __builtin_ctzll(mc);
-                mc &= mc - 1;
-                const float4 q = stage[tbl[w][c][j]];
-                const float d0 = me.x - q.x, d1 = me.y - q.y, d2 = me.z - q.z;
-                const float W = kernel_W_fast(kernel, d0 * d0 + d1 * d1 + d2 * d2, inv_h, wnorm);
-                sw.add(W);
-                su.add(q.w != me.w ? W : 0.0f);
-            }
+        // a per-lane trip count (lanes leave as they finish), two hits per trip so that the
+        // compensated sums alternate registers instead of being copied back each hit
+#pragma unroll 2
+        for (uint32_t i = 0; i < cnt; i++) {
+            while (mc == 0) mc = mrow[++c];
+            const int j = __builtin_ctzll(mc);
+            mc &= mc - 1;
+            const float4 q = stage[tbl[w][c][j]];
+            const float d0 = me.x - q.x, d1 = me.y - q.y, d2 = me.z - q.z;
+            const float W = kernel_W_fast(kernel, d0 * d0 + d1 * d1 + d2 * d2, inv_h, wnorm);
+            sw.add(W);
+            su.add(q.w != me.w ? W : 0.0f);
         }
         const double SW = group_total(sw.s, KAHAN ? sw.c : 0.0f, lane, (int)ntc, G);
         const double SU = group_total(su.s, KAHAN ? su.c : 0.0f, lane, (int)ntc, G);
@@ -1391,7 +1401,7 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
     __shared__ BrickFrame F;
     __shared__ float4 SA[kStageForce];   // position (brick frame), P/rho^2
     __shared__ float4 SB[kStageForce];   // velocity - v_ref, V (negative: viscous species)
-    __shared__ float4 SC[kStageForce];   // spin, V/S
+    __shared__ float4 SC[kStageForce];   // half the spin, V/S
     __shared__ double vref[3];
     __shared__ int16_t tbl[kBrickThreads / 64][kCandWin][64];
     const uint32_t brick = brick_of_workgroup(blockIdx.x, gridDim.x);
@@ -1437,13 +1447,8 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
         const bool fluid = target && (SK[p] >> 1) == KIND_FLUID;
         const uint32_t ki = toff + chunk + tt;
         const float4 Ai = SA[ki], Bi = SB[ki], Ci = SC[ki];
-        ForceP<float> I;
-        I.sp = Bi.w < 0.0f ? 1 : 0;
-        I.m = I.sp ? K.m1 : K.m0;
-        I.V = fabsf(Bi.w);
-        I.Pr = Ai.w;
-        I.ir2 = I.V * I.V * (I.sp ? im2_1 : im2_0);
-        I.VS = Ci.w;
+        const ForceI32 I = force_target(K, Ai, Bi, Ci, im2_0, im2_1);
+        const int spi = Bi.w < 0.0f ? 1 : 0;
         // all of the target's mask words at once (no chain of dependent loads); group g
         // takes hits [lo, lo + cnt), starting in window c
         const uint64_t *gm = s.masks + (size_t)p * kMaskSlots;
@@ -1473,33 +1478,25 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
             if (cc == c + 1) nxt = mw[cc];
         }
         if (cnt) mc = drop_low_bits(mc, lo - before);
-        const uint32_t most = wave_max(cnt);
         Acc<float, KAHAN> F0, F1, F2, T0, T1, T2;
-        for (uint32_t i = 0; i < most; i++) {
-            if (i < cnt) {
-                while (mc == 0) {
-                    mc = nxt;
-                    ++c;
-                    nxt = c + 1 < NW ? gm[c + 1] : 0ull;
-                }
-                const int j = __builtin_ctzll(mc);
-                mc &= mc - 1;
-                const uint32_t k = (uint32_t)tbl[w][c][j];
-                const float4 A = SA[k], B = SB[k], C = SC[k];
-                ForceP<float> J;
-                J.sp = B.w < 0.0f ? 1 : 0;
-                J.m = J.sp ? K.m1 : K.m0;
-                J.V = fabsf(B.w);
-                J.Pr = A.w;
-                J.ir2 = J.V * J.V * (J.sp ? im2_1 : im2_0);
-                J.VS = C.w;
-                float f[3], n[3];
-                pair_force_f32(K, I, J, Ai.x - A.x, Ai.y - A.y, Ai.z - A.z, Bi.x - B.x, Bi.y - B.y,
-                               Bi.z - B.z, 0.5f * (Ci.x + C.x), 0.5f * (Ci.y + C.y),
-                               0.5f * (Ci.z + C.z), f, n);
-                F0.add(f[0]); F1.add(f[1]); F2.add(f[2]);
-                T0.add(n[0]); T1.add(n[1]); T2.add(n[2]);
+        // per-lane trip count, two hits per trip (as in the density sweep)
+#pragma unroll 2
+        for (uint32_t i = 0; i < cnt; i++) {
+            while (mc == 0) {
+                mc = nxt;
+                ++c;
+                nxt = c + 1 < NW ? gm[c + 1] : 0ull;
             }
+            const int j = __builtin_ctzll(mc);
+            mc &= mc - 1;
+            const uint32_t k = (uint32_t)tbl[w][c][j];
+            const float4 A = SA[k], B = SB[k], C = SC[k];
+            float f[3], n[3];
+            pair_force_f32(K, I, im2_0, im2_1, A, B, C, Ai.x - A.x, Ai.y - A.y, Ai.z - A.z,
+                           Bi.x - B.x, Bi.y - B.y, Bi.z - B.z, Ci.x + C.x, Ci.y + C.y,
+                           Ci.z + C.z, f, n);
+            F0.add(f[0]); F1.add(f[1]); F2.add(f[2]);
+            T0.add(n[0]); T1.add(n[1]); T2.add(n[2]);
         }
         const double f0 = group_total(F0.s, KAHAN ? F0.c : 0.0f, lane, ntc, G);
         const double f1 = group_total(F1.s, KAHAN ? F1.c : 0.0f, lane, ntc, G);
@@ -1510,7 +1507,7 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
         if (target && g == 0) {
             const double FF[3] = {fluid ? f0 : 0.0, fluid ? f1 : 0.0, fluid ? f2 : 0.0};
             const double TT[3] = {fluid ? t0 : 0.0, fluid ? t1 : 0.0, fluid ? t2 : 0.0};
-            err |= force_finish<float>(s, d, p, I.sp, FF, TT);
+            err |= force_finish<float>(s, d, p, spi, FF, TT);
         }
     }
     if (err) atomicOr(s.err, err);
