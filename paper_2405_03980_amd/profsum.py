@@ -8,11 +8,13 @@ Reads one sub-directory per rocprofv3 run under a root folder:
   fix the factor between each counter and true bytes;
 * ``sq`` -- one pass of SQ_* counters.
 
-Prints a text summary and, with a second argument, writes the per-kernel HBM traffic
-(KiB per dispatch plus the copy calibration) as JSON, stamped with a hash of the kernel
-sources so that a reader can tell when the figures are stale.
+Prints a text summary; with a second argument writes the per-kernel HBM traffic (KiB per
+dispatch plus the copy calibration) as JSON, stamped with a hash of the kernel sources so
+that a reader can tell when the figures are stale; with a third writes the same figures as
+a markdown summary that lists the commands behind them (COMMANDS).
 
-    python -m paper_2405_03980_amd.profsum gpurun_out/prof profiles/counters.json
+    python -m paper_2405_03980_amd.profsum gpurun_out/prof profiles/counters.json \
+        profiles/sweeps_cylinder_19.57M.md
 """
 from __future__ import annotations
 
@@ -25,6 +27,22 @@ import sys
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+BENCH = "python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline --fp64-steps 0 --batch-steps 0"
+COPY = "python3 bench.py --copy-calibration 1024"
+SQ = ("SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_SALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES "
+      "SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_VALU")
+# One rocprofv3 run per sub-directory, from the repository root, with TMPDIR=/tmp.
+COMMANDS = [
+    ("trace", f"rocprofv3 --kernel-trace --stats -d gpurun_out/prof/trace -o run -- {BENCH}"),
+    ("fetch", f"rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof/fetch -o run -- {BENCH}"),
+    ("write", f"rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof/write -o run -- {BENCH}"),
+    ("copyf", f"rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof/copyf -o run -- {COPY}"),
+    ("copyw", f"rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof/copyw -o run -- {COPY}"),
+    ("sq", f"rocprofv3 --pmc {SQ} -d gpurun_out/prof/sq -o run -- {BENCH}"),
+]
+# VALU instruction issue capacity: 256 CUs x 4 SIMDs, one wave64 instruction per 4 cycles
+# on a 16-lane SIMD, at 2.4 GHz.
+VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
 COPY_MIB = 1024
 KERNEL_GROUPS = {"k_keys<float>": "keys", "k_scatter": "scatter", "k_reorder<float>": "reorder",
                  "k_density_cand<true>": "density", "k_force_cand<true>": "force",
@@ -58,8 +76,10 @@ def _avg(c, kernel, counter):
     return sum(v) / len(v) if v else None
 
 
-def summarize(root: str, out_json: str | None = None, workload: str = "") -> dict:
+def summarize(root: str, out_json: str | None = None, workload: str = "",
+              out_md: str | None = None) -> dict:
     allc = {}
+    trace = []
     for sub in sorted(os.listdir(root)):
         dbs = glob.glob(os.path.join(root, sub, "**", "*.db"), recursive=True)
         if not dbs:
@@ -68,6 +88,7 @@ def summarize(root: str, out_json: str | None = None, workload: str = "") -> dic
         if sub == "trace":
             con = sqlite3.connect(dbs[0])
             for r in con.execute("select name, total_calls, average, percentage from top_kernels"):
+                trace.append((_short(r[0]), int(r[1]), float(r[2]), float(r[3])))
                 print(f"  {_short(r[0]):28s} calls={r[1]:4d} avg_us={r[2]:10.1f}"
                       f" share={r[3]:5.1f}%")
             continue
@@ -98,10 +119,54 @@ def summarize(root: str, out_json: str | None = None, workload: str = "") -> dic
             with open(out_json, "w") as fh:
                 json.dump(res, fh, indent=1)
             print("wrote", out_json)
+        if out_md:
+            with open(out_md, "w") as fh:
+                fh.write(_markdown(res, trace))
+            print("wrote", out_md)
     return res
+
+
+def _markdown(res: dict, trace: list) -> str:
+    avg_us = {name: us for name, _, us, _ in trace}
+    out = [f"# rocprofv3: {res['workload']}", "",
+           f"Kernel sources: `{res['source_sha']}` (sha256 prefix of `csrc/kernels.hip` + "
+           "`csrc/sph_device.h`).", "",
+           "Commands (repository root, `TMPDIR=/tmp`, one run each):", "", "```"]
+    out += [c for _, c in COMMANDS]
+    out += ["python3 -m paper_2405_03980_amd.profsum gpurun_out/prof profiles/counters.json "
+            "profiles/<this file>", "```", "",
+            "## Kernel trace (`--kernel-trace --stats`)", "",
+            "| kernel | calls | mean us | share |", "|---|---|---|---|"]
+    out += [f"| `{n}` | {c} | {us:.1f} | {sh:.1f}% |" for n, c, us, sh in trace]
+    out += ["", "## HBM traffic per launch", "",
+            f"Copy calibration: a {res['copy_MiB']} MiB device copy reads FETCH_SIZE = "
+            f"{res['copy_FETCH_SIZE_KiB']:.0f} KiB and WRITE_SIZE = "
+            f"{res['copy_WRITE_SIZE_KiB']:.0f} KiB, so the factors are "
+            f"{res['fetch_scale']:.4f} (fetch) and {res['write_scale']:.4f} (write).", "",
+            "| group | kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled GB | GB/s at mean time |",
+            "|---|---|---|---|---|---|"]
+    for g, k in res["kernels"].items():
+        gb = 1024.0 * (k["FETCH_SIZE_KiB"] * res["fetch_scale"]
+                       + k["WRITE_SIZE_KiB"] * res["write_scale"]) / 1e9
+        us = avg_us.get(k["kernel"])
+        bw = f"{gb / (us * 1e-6):.0f}" if us else "-"
+        out.append(f"| {g} | `{k['kernel']}` | {k['FETCH_SIZE_KiB']:.0f} | "
+                   f"{k['WRITE_SIZE_KiB']:.0f} | {gb:.2f} | {bw} |")
+    out += ["", "## SQ counters per launch", "",
+            "VALU issue = SQ_INSTS_VALU / (mean time x "
+            f"{VALU_ISSUE_PER_S:.3e} wave64 instructions/s).", "",
+            "| group | VALU insts | SALU insts | LDS insts | LDS bank-conflict cycles | "
+            "VALU issue |", "|---|---|---|---|---|---|"]
+    for g, c in res["sq"].items():
+        us = avg_us.get(res["kernels"].get(g, {}).get("kernel", ""))
+        util = f"{100 * c['SQ_INSTS_VALU'] / (us * 1e-6 * VALU_ISSUE_PER_S):.0f}%" if us else "-"
+        out.append(f"| {g} | {c['SQ_INSTS_VALU']:.3e} | {c['SQ_INSTS_SALU']:.3e} | "
+                   f"{c['SQ_INSTS_LDS']:.3e} | {c['SQ_LDS_BANK_CONFLICT']:.3e} | {util} |")
+    return "\n".join(out) + "\n"
 
 
 if __name__ == "__main__":
     summarize(sys.argv[1] if len(sys.argv) > 1 else "gpurun_out/prof",
               sys.argv[2] if len(sys.argv) > 2 else None,
-              "cylinder nz=184 (19,567,296 particles), FP32-mixed, tuned launch")
+              "cylinder nz=184 (19,567,296 particles), FP32-mixed, tuned launch",
+              sys.argv[3] if len(sys.argv) > 3 else None)
