@@ -1,10 +1,11 @@
 """Parity at the full sizes of the measured workloads, in the launch configuration the
 benchmark times (the tuned settings of paper_2405_03980_amd/tuned.json).
 
-2.45M-particle cylinder: every fluid particle against the oracle after full steps.
-19.57M-particle cylinder: sampled particles against the oracle evaluated one by one, and
-one full step of every particle.  64-instance batch: every instance against its own
-single-instance run.
+2.45M-particle cylinder: every fluid particle against the oracle after one and two steps,
+and a stored sample of the oracle's state after 100 steps.  19.57M-particle cylinder:
+sampled particles against the oracle evaluated one by one, one full step of every
+particle, and 100 steps of the FP32-mixed path against the FP64 path.  64-instance batch:
+every instance against its own single-instance run.
 """
 import json
 import os
@@ -174,3 +175,64 @@ def test_batch64_equals_single_instances():
         assert positions_ok(e, 1e-5, 4), e
         for k in ("v", "omega", "rho"):
             assert e[k] < 1e-5, (i, k, e[k])
+
+
+GOLD100 = os.path.join(ROOT, "tests", "golden", "cylinder_2p45M_100steps.npz")
+
+
+def _norm(a):
+    return np.sqrt((a * a).sum(axis=0)) if a.ndim == 2 else np.abs(a)
+
+
+@pytest.mark.parametrize("prec,tol", [(L.FP64, 1e-12), (L.FP32_MIXED, 1e-3)])
+def test_cylinder_2p45M_100_steps_vs_oracle(prec, tol):
+    """100 steps of the 2.45M cylinder against the oracle's state after 100 steps: a seeded
+    sample of 5,000 fluid particles (3,000 anywhere, 2,000 next to the wall) stored by
+    tests/golden/make_cylinder_2p45M_100.py, normwise errors over the oracle's whole-field
+    maxima.  FP64 path within 1e-12 on every field, FP32-mixed within 1e-3."""
+    g = np.load(GOLD100, allow_pickle=False)
+    w = I.config(1)
+    steps = int(g["steps"])
+    print(f"[full] cylinder 2.45M, {steps} steps, prec={prec}", flush=True)
+    s = _sim(w, prec, "cylinder_nz92")
+    s.step(float(g["dt"]), w.Omega, steps)
+    out = s.read(("x", "v", "omega", "rho", "P", "acc", "alpha"))
+    s.close()
+    del s
+    ids = g["ids"]
+    p = w.params
+    B = p["rho0"] * p["c0"] ** 2 / 7.0
+    H = p["hi"][2] - p["lo"][2]
+    dx = out["x"][:, ids] - g["x"]
+    dx[2] -= H * np.round(dx[2] / H)
+    e = {"x": float(_norm(dx).max() / g["disp_max"]),
+         "x_ulp": float((np.abs(dx) / np.spacing(np.abs(g["x"]))).max()),
+         "rho": float(np.abs(out["rho"][ids] - g["rho"]).max() / g["rho_max"]),
+         "P": float(np.abs(out["P"][ids] - g["P"]).max() / B)}
+    for k in ("v", "omega", "acc", "alpha"):
+        e[k] = float(_norm(out[k][:, ids] - g[k]).max() / g[k + "_max"])
+    print(f"2.45M {steps} steps prec={prec}", e, flush=True)
+    assert positions_ok(e, tol, steps), e
+    fields = ("v", "omega", "rho", "P", "acc", "alpha") if prec == L.FP64 else ("v", "omega", "rho", "P")
+    for k in fields:
+        assert e[k] < tol, (k, e[k])
+
+
+def test_cylinder_19p57M_mixed_vs_fp64_100_steps(cyl1957):
+    """The benchmarked workload over 100 steps: the FP32-mixed path against the FP64 GPU path
+    (which the tests above tie to the oracle), within 1e-3 on positions, velocities, spins,
+    density and pressure."""
+    w = cyl1957
+    outs = {}
+    for prec in (L.FP64, L.FP32_MIXED):
+        print(f"[full] cylinder 19.57M, 100 steps, prec={prec}", flush=True)
+        s = _sim(w, prec, "cylinder_nz184")
+        s.step(1e-4, w.Omega, 100)
+        outs[prec] = s.read(("x", "v", "omega", "rho", "P", "acc", "alpha"))
+        s.close()
+        del s
+    e = field_errors(outs[L.FP32_MIXED], _Snap(outs[L.FP64]), w)
+    print("19.57M mixed vs fp64, 100 steps", e, flush=True)
+    assert positions_ok(e, 1e-3, 100), e
+    for k in ("v", "omega", "rho", "P"):
+        assert e[k] < 1e-3, (k, e[k])
