@@ -38,7 +38,7 @@ DENSITY_FLOPS_PER_PAIR = 19
 BYTES_PER_PARTICLE = {
     "keys": 24 + 24 + 12 + 1 + 4 + 4,          # x, v, acc, sk -> key, slot
     "scan": 0.0,                                # per cell, counted below
-    "scatter": 4 + 4 + 4 + 4,                   # key, slot, start -> tmp
+    "scatter": 4 + 4 + 4 + 4 + 4 + 4,           # key, slot, start, id -> tmp, idt
     "reorder": 4 + 4 + 4 + 72 + 24 + 1 + 72 + 4 + 1 + 4,  # tmp, key, id, state -> state, pcell
     "density": 24 + 1 + 4 + 4 + 16 + 8,         # x, sk, pcell, cell_xyz -> aux, rho/P
     "force": 72 + 16 + 1 + 4 + 4 + 24,          # x, v, w, aux, sk, pcell, cell -> acc, alpha

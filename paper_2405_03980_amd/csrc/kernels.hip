@@ -304,6 +304,7 @@ __global__ void k_scatter(DevState s)
     uint32_t p = t.p;
     uint32_t pos = s.start[s.key[p]] + s.slot[p];
     s.tmp[pos] = p;
+    s.idt[pos] = s.id[s.cur][p];
 }
 
 // Final position = cell start + rank of the particle id within its cell, so the order is
@@ -319,11 +320,12 @@ __global__ void k_reorder(DevState s, int mode, double kick, double dt)
     uint32_t op = s.tmp[q];
     uint32_t c = s.key[op];
     uint32_t b = s.start[c], e = s.start[c + 1];
-    uint32_t myid = s.id[cur][op];
+    uint32_t myid = s.idt[q];
     uint32_t dst = q;
     if (e - b <= (uint32_t)kMaxCell) {
+        // the cell's ids in scatter order are contiguous: one independent load per member
         uint32_t rank = 0;
-        for (uint32_t k = b; k < e; k++) rank += s.id[cur][s.tmp[k]] < myid ? 1u : 0u;
+        for (uint32_t k = b; k < e; k++) rank += s.idt[k] < myid ? 1u : 0u;
         dst = b + rank;
     } else {
         atomicOr(s.err, (uint32_t)ERR_CAPACITY);
@@ -1333,15 +1335,17 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
             const uint32_t kt = toff + t0 + t;
             const float4 T = stage[kt];
             const uint32_t vs = stencil_self(S, kt);
-            const bool mine = (uint32_t)lane == t;
+            uint32_t mine = (uint32_t)lane == t ? ~0u : 0u;
+            asm volatile("" : "+v"(mine));  // an opaque lane mask, so that the updates below
+                                            // stay one and-or instead of becoming selects
 #pragma unroll
             for (int c = 0; c < kCandWin; c++) {
                 if (c < (int)S.NW) {
                     const float d0 = cx[c] - T.x, d1 = cy[c] - T.y, d2 = cz[c] - T.z;
                     uint64_t m = __ballot(d0 * d0 + d1 * d1 + d2 * d2 < cut2);
                     if ((vs >> 6) == (uint32_t)c) m &= ~(1ull << (vs & 63));
-                    mlo[c] = mine ? (uint32_t)m : mlo[c];
-                    mhi[c] = mine ? (uint32_t)(m >> 32) : mhi[c];
+                    mlo[c] |= mine & (uint32_t)m;  // lane t keeps target t's masks
+                    mhi[c] |= mine & (uint32_t)(m >> 32);
                 }
             }
         }
@@ -1370,18 +1374,25 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
         hit_share([&](int cc) { return mrow[cc]; }, act ? H : 0u, g, G, cnt, c, mc);
         const float4 me = stage[toff + t0 + tt];
         Acc<float, KAHAN> sw, su;
+        // the next hit's table and stage reads are issued before this hit's arithmetic, so
+        // the chain of dependent LDS reads overlaps it
+        auto next_hit = [&]() {
+            while (mc == 0) mc = mrow[++c];
+            const int j = __builtin_ctzll(mc);
+            mc &= mc - 1;
+            return stage[tbl[w][c][j]];
+        };
+        float4 q = cnt ? next_hit() : me;
         // a per-lane trip count (lanes leave as they finish), two hits per trip so that the
         // compensated sums alternate registers instead of being copied back each hit
 #pragma unroll 2
         for (uint32_t i = 0; i < cnt; i++) {
-            while (mc == 0) mc = mrow[++c];
-            const int j = __builtin_ctzll(mc);
-            mc &= mc - 1;
-            const float4 q = stage[tbl[w][c][j]];
-            const float d0 = me.x - q.x, d1 = me.y - q.y, d2 = me.z - q.z;
+            const float4 qc = q;
+            if (i + 1 < cnt) q = next_hit();
+            const float d0 = me.x - qc.x, d1 = me.y - qc.y, d2 = me.z - qc.z;
             const float W = kernel_W_fast(kernel, d0 * d0 + d1 * d1 + d2 * d2, inv_h, wnorm);
             sw.add(W);
-            su.add(q.w != me.w ? W : 0.0f);
+            su.add(qc.w != me.w ? W : 0.0f);
         }
         const double SW = group_total(sw.s, KAHAN ? sw.c : 0.0f, lane, (int)ntc, G);
         const double SU = group_total(su.s, KAHAN ? su.c : 0.0f, lane, (int)ntc, G);
@@ -1480,8 +1491,7 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
         if (cnt) mc = drop_low_bits(mc, lo - before);
         Acc<float, KAHAN> F0, F1, F2, T0, T1, T2;
         // per-lane trip count, two hits per trip (as in the density sweep)
-#pragma unroll 2
-        for (uint32_t i = 0; i < cnt; i++) {
+        auto next_k = [&]() {
             while (mc == 0) {
                 mc = nxt;
                 ++c;
@@ -1489,8 +1499,14 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
             }
             const int j = __builtin_ctzll(mc);
             mc &= mc - 1;
-            const uint32_t k = (uint32_t)tbl[w][c][j];
+            return (uint32_t)tbl[w][c][j];
+        };
+        uint32_t kn = cnt ? next_k() : 0u;  // the next hit's index, decoded a hit ahead
+#pragma unroll 2
+        for (uint32_t i = 0; i < cnt; i++) {
+            const uint32_t k = kn;
             const float4 A = SA[k], B = SB[k], C = SC[k];
+            if (i + 1 < cnt) kn = next_k();
             float f[3], n[3];
             pair_force_f32(K, I, im2_0, im2_1, A, B, C, Ai.x - A.x, Ai.y - A.y, Ai.z - A.z,
                            Bi.x - B.x, Bi.y - B.y, Bi.z - B.z, Ci.x + C.x, Ci.y + C.y,

@@ -163,6 +163,7 @@ void carve(Carver &c, DevState &d, int n_inst, uint32_t N, uint32_t C, uint32_t 
     d.key = c.take<uint32_t>(N);
     d.slot = c.take<uint32_t>(N);
     d.tmp = c.take<uint32_t>(N);
+    d.idt = c.take<uint32_t>(N);
     d.pcell = c.take<uint32_t>(N);
     d.count = c.take<uint32_t>(C);
     d.start = c.take<uint32_t>((size_t)C + 1);
