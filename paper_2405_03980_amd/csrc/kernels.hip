@@ -660,48 +660,77 @@ typedef int16_t WindowTable[kBrickThreads / 64][kMergeWin][64];
 
 __device__ __forceinline__ int slot_index(int x, int y, int z) { return x + 4 * (y + 4 * z); }
 
-// Fills the frame (wave 0: one lane per slot, a wave-level scan for the offsets) and
-// returns the staged particle count; F.ok tells whether they fit stage_max.  With Vv, the lane of slot (1,1,1), the brick's
-// first cell, also loads the velocity of that cell's first particle into vref.
-__device__ __forceinline__ uint32_t brick_frame(const DevState &s, const InstDesc *d, uint32_t bxyz,
-                                            BrickFrame &F, int stage_max,
+// Slot t (x + 4y + 16z over the 4x4x4 neighbourhood) of brick bxyz: its cell (wrapped on
+// periodic axes, with the image shift in sh) and whether the cell lies in the grid.
+__device__ __forceinline__ bool slot_cell(const InstDesc *d, uint32_t bxyz, int t, int c[3], double sh[3])
+{
+    const int b[3] = {(int)(bxyz & 1023), (int)((bxyz >> 10) & 1023), (int)(bxyz >> 20)};
+    const int i[3] = {t & 3, (t >> 2) & 3, t >> 4};
+    bool valid = true;
+    for (int a = 0; a < 3; a++) {
+        c[a] = 2 * b[a] + i[a] - 1;
+        sh[a] = 0.0;
+        if (d->periodic[a]) {
+            if (c[a] < 0) { c[a] += d->n[a]; sh[a] = -d->L[a]; }
+            else if (c[a] >= d->n[a]) { c[a] -= d->n[a]; sh[a] = d->L[a]; }
+        } else if (c[a] < 0 || c[a] >= d->n[a]) {
+            valid = false;
+        }
+    }
+    return valid;
+}
+
+// The frames of all bricks, once per step (after the cell list): per brick, the sorted index
+// of each slot's first particle and the inclusive prefix of the slot counts, [64] + [64]
+// words.  The brick sweeps then set up a brick with one coalesced load instead of a chain
+// of dependent loads through the cell tables.
+__global__ void __launch_bounds__(64) k_brick_frames(DevState s)
+{
+    const uint32_t brick = blockIdx.x;
+    const int t = threadIdx.x;
+    const InstDesc *d = s.desc + s.brick_inst[brick];
+    int c[3];
+    double sh[3];
+    uint32_t beg = 0, cnt = 0;
+    if (slot_cell(d, s.brick_xyz[brick], t, c, sh)) {
+        const uint32_t lin = (uint32_t)c[0] + (uint32_t)d->n[0] * ((uint32_t)c[1] + (uint32_t)d->n[1] * (uint32_t)c[2]);
+        const uint32_t r = s.rank_of_lin[d->cell_off + lin];
+        beg = s.start[r];
+        cnt = s.start[r + 1] - beg;
+    }
+    uint32_t inc = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o);
+        if (t >= o) inc += y;
+    }
+    s.bframe[(size_t)brick * 128 + t] = beg;
+    s.bframe[(size_t)brick * 128 + 64 + t] = inc;
+}
+
+// Fills the frame from the brick's precomputed slots (wave 0: one lane per slot) and returns
+// the staged particle count; F.ok tells whether they fit stage_max.  With Vv, the lane of
+// slot (1,1,1), the brick's first cell, also loads the velocity of that cell's first
+// particle into vref.
+__device__ __forceinline__ uint32_t brick_frame(const DevState &s, const InstDesc *d, uint32_t brick,
+                                            uint32_t bxyz, BrickFrame &F, int stage_max,
                                             const double *Vv = nullptr, double *vref = nullptr)
 {
     const int t = threadIdx.x;
-    const int b[3] = {(int)(bxyz & 1023), (int)((bxyz >> 10) & 1023), (int)(bxyz >> 20)};
     if (t < 64) {
-        const int i[3] = {t & 3, (t >> 2) & 3, t >> 4};
+        const uint32_t beg = s.bframe[(size_t)brick * 128 + t];
+        const uint32_t inc = s.bframe[(size_t)brick * 128 + 64 + t];
         int c[3];
-        bool valid = true;
-        for (int a = 0; a < 3; a++) {
-            c[a] = 2 * b[a] + i[a] - 1;
-            double sh = 0.0;
-            if (d->periodic[a]) {
-                if (c[a] < 0) { c[a] += d->n[a]; sh = -d->L[a]; }
-                else if (c[a] >= d->n[a]) { c[a] -= d->n[a]; sh = d->L[a]; }
-            } else if (c[a] < 0 || c[a] >= d->n[a]) {
-                valid = false;
-            }
-            F.shift[t][a] = sh;
-        }
-        uint32_t beg = 0, cnt = 0;
-        if (valid) {
-            uint32_t lin = (uint32_t)c[0] + (uint32_t)d->n[0] * ((uint32_t)c[1] + (uint32_t)d->n[1] * (uint32_t)c[2]);
-            uint32_t r = s.rank_of_lin[d->cell_off + lin];
-            beg = s.start[r];
-            cnt = s.start[r + 1] - beg;
-        }
+        double sh[3];
+        slot_cell(d, bxyz, t, c, sh);
+        for (int a = 0; a < 3; a++) F.shift[t][a] = sh[a];
+        const uint32_t below = __shfl_up(inc, 1);
+        const uint32_t cnt = inc - (t ? below : 0u);
         F.begin[t] = beg;
-        uint32_t inc = cnt;
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(inc, o);
-            if (t >= o) inc += y;
-        }
         F.off[t + 1] = inc;
         if (t == 0) F.off[0] = 0;
         const bool over = __any(cnt > (uint32_t)kMaxCell);
         if (t == 63) F.ok = !over && inc <= (uint32_t)stage_max;
-        if (t < 3) F.origin[t] = d->lo[t] + (double)(2 * b[t] + 1) * d->edge[t];
+        if (t < 3) F.origin[t] = d->lo[t] + (double)(2 * (int)((bxyz >> (10 * t)) & 1023) + 1) * d->edge[t];
         if (Vv && t == slot_index(1, 1, 1))
             for (int a = 0; a < 3; a++) vref[a] = cnt ? Vv[(size_t)a * s.N + beg] : 0.0;
     }
@@ -1020,10 +1049,11 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_brick(DevState s)
     __shared__ BrickFrame F;
     __shared__ WindowTable win;
     __shared__ float4 stage[kStageDensity];
-    const uint32_t bxyz = s.brick_xyz[blockIdx.x];
-    const InstDesc *d = s.desc + s.brick_inst[blockIdx.x];
+    const uint32_t brick = blockIdx.x;
+    const uint32_t bxyz = s.brick_xyz[brick];
+    const InstDesc *d = s.desc + s.brick_inst[brick];
     const uint8_t *SK = s.sk[s.cur];
-    brick_frame(s, d, bxyz, F, kStageDensity);
+    brick_frame(s, d, brick, bxyz, F, kStageDensity);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int ts[3];
     const bool has_cell = brick_target(d, bxyz, w, ts);
@@ -1098,10 +1128,11 @@ __global__ void __launch_bounds__(kBrickThreads) k_force_brick(DevState s)
     __shared__ float4 SB[kStageForce];   // velocity - v_ref, V (negative: viscous species)
     __shared__ float4 SC[kStageForce];   // half the spin, V/S
     __shared__ double vref[3];
-    const uint32_t bxyz = s.brick_xyz[blockIdx.x];
-    const InstDesc *d = s.desc + s.brick_inst[blockIdx.x];
+    const uint32_t brick = blockIdx.x;
+    const uint32_t bxyz = s.brick_xyz[brick];
+    const InstDesc *d = s.desc + s.brick_inst[brick];
     const uint8_t *SK = s.sk[s.cur];
-    const uint32_t M = brick_frame(s, d, bxyz, F, kStageForce, s.v[s.cur], vref);
+    const uint32_t M = brick_frame(s, d, brick, bxyz, F, kStageForce, s.v[s.cur], vref);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int ts[3];
     const bool has_cell = brick_target(d, bxyz, w, ts);
@@ -1285,7 +1316,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
     const uint32_t bxyz = s.brick_xyz[brick];
     const InstDesc *d = s.desc + s.brick_inst[brick];
     const uint8_t *SK = s.sk[s.cur];
-    brick_frame(s, d, bxyz, F, kStageDensity);
+    brick_frame(s, d, brick, bxyz, F, kStageDensity);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int ts[3];
     const bool has_cell = brick_target(d, bxyz, w, ts);
@@ -1419,7 +1450,7 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
     const uint32_t bxyz = s.brick_xyz[brick];
     const InstDesc *d = s.desc + s.brick_inst[brick];
     const uint8_t *SK = s.sk[s.cur];
-    const uint32_t M = brick_frame(s, d, bxyz, F, kStageForce, s.v[s.cur], vref);
+    const uint32_t M = brick_frame(s, d, brick, bxyz, F, kStageForce, s.v[s.cur], vref);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int ts[3];
     const bool has_cell = brick_target(d, bxyz, w, ts);
@@ -1770,8 +1801,11 @@ hipError_t launch_density(const DevState &d, const Launch &L, hipStream_t st)
 {
     unsigned g = grid_for(d.n_waves, L.bs_density);
     if (d.precision == 0) k_density<double, false><<<g, L.bs_density, 0, st>>>(d);
-    else if (L.sweep == SWEEP_BRICK && d.n_bricks) k_density_brick<true><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
-    else if (L.sweep == SWEEP_CAND && d.n_bricks) k_density_cand<true><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
+    else if ((L.sweep == SWEEP_BRICK || L.sweep == SWEEP_CAND) && d.n_bricks) {
+        k_brick_frames<<<d.n_bricks, 64, 0, st>>>(d);
+        if (L.sweep == SWEEP_BRICK) k_density_brick<true><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
+        else k_density_cand<true><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
+    }
     else k_density<float, true><<<g, L.bs_density, 0, st>>>(d);
     return hipGetLastError();
 }

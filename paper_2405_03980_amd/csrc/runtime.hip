@@ -177,6 +177,7 @@ void carve(Carver &c, DevState &d, int n_inst, uint32_t N, uint32_t C, uint32_t 
     d.brick_inst = c.take<uint32_t>(NB ? NB : 1);
     d.n_bricks = NB;
     d.masks = c.take<uint64_t>((NB && precision == SPH_FP32_MIXED) ? (size_t)N * kMaskSlots : 1);
+    d.bframe = c.take<uint32_t>((NB && precision == SPH_FP32_MIXED) ? (size_t)NB * 128 : 1);
 }
 
 struct Plan {

@@ -58,6 +58,7 @@ struct DevState {
     void *rhoP;                   // [N][2]: rho, P
     uint32_t *key, *slot, *tmp, *pcell;
     uint32_t *idt;                // id of the particle at each scatter position (= id[tmp[.]])
+    uint32_t *bframe;             // [n_bricks][128]: slot first indices, inclusive slot-count prefix
     uint32_t *count, *start, *bsum;
     uint32_t *cell_xyz;           // global cell rank -> packed (cx | cy << 10 | cz << 20)
     uint32_t *rank_of_lin;        // cell_off + linear cell index -> global cell rank
