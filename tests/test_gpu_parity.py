@@ -191,6 +191,22 @@ def test_graph_replay_equals_eager(prec):
     b.close()
 
 
+@pytest.mark.parametrize("prec", [FP64, MIXED])
+def test_runs_are_bitwise_reproducible(prec):
+    """Two independent simulations of the same input give identical bits: every summation
+    order is fixed (cell order by id, fixed group trees, no floating-point atomics)."""
+    w = I.make_cylinder(40, seed=(3980, 2))
+    print(f"[repro] prec={prec} n={w.n}", flush=True)
+    outs = []
+    for _ in range(2):
+        s = _sim(w, prec)
+        s.step(1e-4, w.Omega, 5)
+        outs.append(s.read())
+        s.close()
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
 def test_resume_from_checkpoint():
     """read_fields -> init_particles round trip: the fields come back unchanged, and a
     resumed run tracks the oracle resumed from its own checkpoint.  (Resuming is not
