@@ -1305,6 +1305,29 @@ __device__ __forceinline__ float kernel_W_fast(int kernel, float r2, float inv_h
     return wnorm * 0.25f * t * t * t;
 }
 
+// Ballot tests of targets kbase .. kbase + ntc - 1 (staged indices) against the first NWc
+// candidate windows, NWc fixed at compile time so that the windows need no branch per
+// target.  Lane t ORs target t's masks into mlo/mhi (low and high halves).
+template <int NWc>
+__device__ __forceinline__ void test_targets(const float4 *stage, const float *cx, const float *cy,
+                                             const float *cz, uint32_t kbase, uint32_t ntc,
+                                             float cut2, int lane, uint32_t *mlo, uint32_t *mhi)
+{
+    for (uint32_t t = 0; t < ntc; t++) {
+        const float4 T = stage[kbase + t];
+        uint32_t mine = (uint32_t)lane == t ? ~0u : 0u;
+        asm volatile("" : "+v"(mine));  // an opaque lane mask, so that the updates below
+                                        // stay one and-or instead of becoming selects
+#pragma unroll
+        for (int c = 0; c < NWc; c++) {
+            const float d0 = cx[c] - T.x, d1 = cy[c] - T.y, d2 = cz[c] - T.z;
+            const uint64_t m = __ballot(d0 * d0 + d1 * d1 + d2 * d2 < cut2);
+            mlo[c] |= mine & (uint32_t)m;
+            mhi[c] |= mine & (uint32_t)(m >> 32);
+        }
+    }
+}
+
 template <bool KAHAN>
 __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
 {
@@ -1362,21 +1385,28 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
         uint32_t mlo[kCandWin], mhi[kCandWin];
 #pragma unroll
         for (int c = 0; c < kCandWin; c++) mlo[c] = mhi[c] = 0u;
-        for (uint32_t t = 0; t < ntc; t++) {
-            const uint32_t kt = toff + t0 + t;
-            const float4 T = stage[kt];
-            const uint32_t vs = stencil_self(S, kt);
-            uint32_t mine = (uint32_t)lane == t ? ~0u : 0u;
-            asm volatile("" : "+v"(mine));  // an opaque lane mask, so that the updates below
-                                            // stay one and-or instead of becoming selects
+        switch (S.NW) {
+        case 1: test_targets<1>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+        case 2: test_targets<2>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+        case 3: test_targets<3>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+        case 4: test_targets<4>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+        case 5: test_targets<5>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+        case 6: test_targets<6>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+        case 7: test_targets<7>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+        case 8: test_targets<8>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+        case 9: test_targets<9>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+        default: test_targets<10>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+        }
+        static_assert(kCandWin == 10, "one case per window count");
+        // a target is not its own neighbour: its lane clears the bit of its list position
+        if ((uint32_t)lane < ntc) {
+            const uint32_t vs = stencil_self(S, toff + t0 + (uint32_t)lane);
+            const uint32_t keep = ~(1u << (vs & 31));
 #pragma unroll
             for (int c = 0; c < kCandWin; c++) {
-                if (c < (int)S.NW) {
-                    const float d0 = cx[c] - T.x, d1 = cy[c] - T.y, d2 = cz[c] - T.z;
-                    uint64_t m = __ballot(d0 * d0 + d1 * d1 + d2 * d2 < cut2);
-                    if ((vs >> 6) == (uint32_t)c) m &= ~(1ull << (vs & 63));
-                    mlo[c] |= mine & (uint32_t)m;  // lane t keeps target t's masks
-                    mhi[c] |= mine & (uint32_t)(m >> 32);
+                if ((vs >> 6) == (uint32_t)c) {
+                    if (vs & 32) mhi[c] &= keep;
+                    else mlo[c] &= keep;
                 }
             }
         }
