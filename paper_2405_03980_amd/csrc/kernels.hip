@@ -12,6 +12,7 @@
 //   k_force    pair forces of Eqs. 1-2 and the spin torques.
 // The closing half kick is folded into the next k_keys / k_reorder.
 #include <math.h>
+#include <type_traits>
 
 #include "sph_device.h"
 
@@ -1012,14 +1013,16 @@ __device__ __forceinline__ ForceI32 force_target(const ForceK<float> &k, float4 
 
 // The same pair terms as pair_force from the staged neighbour (A, B, C as in the staging),
 // without branches on the species: the unlike terms are selected, the viscous-viscous one
-// vanishes through ev and max(-B.w, 0) (= V_j for a viscous neighbour, else 0).
+// vanishes through ev and max(-B.w, 0) (= V_j for a viscous neighbour, else 0).  KT fixes
+// the smoothing kernel at compile time (-1: the one in k).
+template <int KT = -1>
 __device__ __forceinline__ void pair_force_f32(const ForceK<float> &k, const ForceI32 &I, float im2_0,
                                                float im2_1, float4 A, float4 B, float4 C, float r0,
                                                float r1, float r2, float v0, float v1, float v2,
                                                float hs0, float hs1, float hs2, float f[3], float n[3])
 {
     float W, Fk;
-    kernel_WF_fast(k.kernel, r0 * r0 + r1 * r1 + r2 * r2, k.inv_h, k.wnorm, W, Fk);
+    kernel_WF_fast(KT < 0 ? k.kernel : KT, r0 * r0 + r1 * r1 + r2 * r2, k.inv_h, k.wnorm, W, Fk);
     const bool spj = B.w < 0.0f;
     const bool unl = B.w * I.xs < 0.0f;
     const float Vj = fabsf(B.w);
@@ -1379,91 +1382,97 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
     }
     const float cut2 = (float)d->cut2, inv_h = (float)d->inv_h, wnorm = (float)d->wnorm;
     const int kernel = d->kernel;
-    for (uint32_t t0 = 0; t0 < nt; t0 += kListTargets) {
-        const uint32_t ntc = min((uint32_t)kListTargets, nt - t0);
-        // test: one target at a time against every window; lane t collects target t's masks
-        uint32_t mlo[kCandWin], mhi[kCandWin];
-#pragma unroll
-        for (int c = 0; c < kCandWin; c++) mlo[c] = mhi[c] = 0u;
-        switch (S.NW) {
-        case 1: test_targets<1>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-        case 2: test_targets<2>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-        case 3: test_targets<3>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-        case 4: test_targets<4>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-        case 5: test_targets<5>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-        case 6: test_targets<6>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-        case 7: test_targets<7>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-        case 8: test_targets<8>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-        case 9: test_targets<9>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-        default: test_targets<10>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-        }
-        static_assert(kCandWin == 10, "one case per window count");
-        // a target is not its own neighbour: its lane clears the bit of its list position
-        if ((uint32_t)lane < ntc) {
-            const uint32_t vs = stencil_self(S, toff + t0 + (uint32_t)lane);
-            const uint32_t keep = ~(1u << (vs & 31));
-#pragma unroll
-            for (int c = 0; c < kCandWin; c++) {
-                if ((vs >> 6) == (uint32_t)c) {
-                    if (vs & 32) mhi[c] &= keep;
-                    else mlo[c] &= keep;
+    // compiled once per smoothing kernel, chosen per brick (as in the force sweep)
+    auto sweep = [&](auto kt) {
+        constexpr int KT = decltype(kt)::value;
+        for (uint32_t t0 = 0; t0 < nt; t0 += kListTargets) {
+            const uint32_t ntc = min((uint32_t)kListTargets, nt - t0);
+            // test: one target at a time against every window; lane t collects target t's masks
+            uint32_t mlo[kCandWin], mhi[kCandWin];
+    #pragma unroll
+            for (int c = 0; c < kCandWin; c++) mlo[c] = mhi[c] = 0u;
+            switch (S.NW) {
+            case 1: test_targets<1>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+            case 2: test_targets<2>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+            case 3: test_targets<3>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+            case 4: test_targets<4>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+            case 5: test_targets<5>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+            case 6: test_targets<6>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+            case 7: test_targets<7>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+            case 8: test_targets<8>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+            case 9: test_targets<9>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+            default: test_targets<10>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+            }
+            static_assert(kCandWin == 10, "one case per window count");
+            // a target is not its own neighbour: its lane clears the bit of its list position
+            if ((uint32_t)lane < ntc) {
+                const uint32_t vs = stencil_self(S, toff + t0 + (uint32_t)lane);
+                const uint32_t keep = ~(1u << (vs & 31));
+    #pragma unroll
+                for (int c = 0; c < kCandWin; c++) {
+                    if ((vs >> 6) == (uint32_t)c) {
+                        if (vs & 32) mhi[c] &= keep;
+                        else mlo[c] &= keep;
+                    }
                 }
             }
-        }
-        if ((uint32_t)lane < ntc) {
-            uint64_t *gm = s.masks + (size_t)(pbase + t0 + lane) * kMaskSlots;
-#pragma unroll
-            for (int c = 0; c < kCandWin; c++) {
-                if (c < (int)S.NW) {
-                    const uint64_t m = ((uint64_t)mhi[c] << 32) | mlo[c];
-                    msk[w][lane][c] = m;
-                    gm[c] = m;
+            if ((uint32_t)lane < ntc) {
+                uint64_t *gm = s.masks + (size_t)(pbase + t0 + lane) * kMaskSlots;
+    #pragma unroll
+                for (int c = 0; c < kCandWin; c++) {
+                    if (c < (int)S.NW) {
+                        const uint64_t m = ((uint64_t)mhi[c] << 32) | mlo[c];
+                        msk[w][lane][c] = m;
+                        gm[c] = m;
+                    }
                 }
             }
+            __builtin_amdgcn_wave_barrier();
+            // kernel sums: lanes (target tt, group g)
+            const int G = 64 / (int)ntc;
+            const int g = lane / (int)ntc, tt = lane % (int)ntc;
+            const bool act = g < G;
+            const uint64_t *mrow = msk[w][tt];
+            uint32_t H = 0;
+            for (int c = 0; c < (int)S.NW; c++) H += (uint32_t)__popcll(mrow[c]);
+            uint32_t cnt;
+            int c;
+            uint64_t mc;
+            hit_share([&](int cc) { return mrow[cc]; }, act ? H : 0u, g, G, cnt, c, mc);
+            const float4 me = stage[toff + t0 + tt];
+            Acc<float, KAHAN> sw, su;
+            // the next hit's table and stage reads are issued before this hit's arithmetic, so
+            // the chain of dependent LDS reads overlaps it
+            auto next_hit = [&]() {
+                while (mc == 0) mc = mrow[++c];
+                const int j = __builtin_ctzll(mc);
+                mc &= mc - 1;
+                return stage[tbl[w][c][j]];
+            };
+            float4 q = cnt ? next_hit() : me;
+            // a per-lane trip count (lanes leave as they finish), two hits per trip so that the
+            // compensated sums alternate registers instead of being copied back each hit
+    #pragma unroll 2
+            for (uint32_t i = 0; i < cnt; i++) {
+                const float4 qc = q;
+                if (i + 1 < cnt) q = next_hit();
+                const float d0 = me.x - qc.x, d1 = me.y - qc.y, d2 = me.z - qc.z;
+                const float W = kernel_W_fast(KT, d0 * d0 + d1 * d1 + d2 * d2, inv_h, wnorm);
+                sw.add(W);
+                su.add(qc.w != me.w ? W : 0.0f);
+            }
+            const double SW = group_total(sw.s, KAHAN ? sw.c : 0.0f, lane, (int)ntc, G);
+            const double SU = group_total(su.s, KAHAN ? su.c : 0.0f, lane, (int)ntc, G);
+            if (act && g == 0) {
+                const uint32_t p = pbase + t0 + tt;
+                const uint8_t ski = SK[p];
+                err |= density_finish<float>(s, d, p, ski & 1, ski >> 1, SW, SU);
+            }
+            __builtin_amdgcn_wave_barrier();  // the masks are rewritten by the next round
         }
-        __builtin_amdgcn_wave_barrier();
-        // kernel sums: lanes (target tt, group g)
-        const int G = 64 / (int)ntc;
-        const int g = lane / (int)ntc, tt = lane % (int)ntc;
-        const bool act = g < G;
-        const uint64_t *mrow = msk[w][tt];
-        uint32_t H = 0;
-        for (int c = 0; c < (int)S.NW; c++) H += (uint32_t)__popcll(mrow[c]);
-        uint32_t cnt;
-        int c;
-        uint64_t mc;
-        hit_share([&](int cc) { return mrow[cc]; }, act ? H : 0u, g, G, cnt, c, mc);
-        const float4 me = stage[toff + t0 + tt];
-        Acc<float, KAHAN> sw, su;
-        // the next hit's table and stage reads are issued before this hit's arithmetic, so
-        // the chain of dependent LDS reads overlaps it
-        auto next_hit = [&]() {
-            while (mc == 0) mc = mrow[++c];
-            const int j = __builtin_ctzll(mc);
-            mc &= mc - 1;
-            return stage[tbl[w][c][j]];
-        };
-        float4 q = cnt ? next_hit() : me;
-        // a per-lane trip count (lanes leave as they finish), two hits per trip so that the
-        // compensated sums alternate registers instead of being copied back each hit
-#pragma unroll 2
-        for (uint32_t i = 0; i < cnt; i++) {
-            const float4 qc = q;
-            if (i + 1 < cnt) q = next_hit();
-            const float d0 = me.x - qc.x, d1 = me.y - qc.y, d2 = me.z - qc.z;
-            const float W = kernel_W_fast(kernel, d0 * d0 + d1 * d1 + d2 * d2, inv_h, wnorm);
-            sw.add(W);
-            su.add(qc.w != me.w ? W : 0.0f);
-        }
-        const double SW = group_total(sw.s, KAHAN ? sw.c : 0.0f, lane, (int)ntc, G);
-        const double SU = group_total(su.s, KAHAN ? su.c : 0.0f, lane, (int)ntc, G);
-        if (act && g == 0) {
-            const uint32_t p = pbase + t0 + tt;
-            const uint8_t ski = SK[p];
-            err |= density_finish<float>(s, d, p, ski & 1, ski >> 1, SW, SU);
-        }
-        __builtin_amdgcn_wave_barrier();  // the masks are rewritten by the next round
-    }
+    };
+    if (kernel == KERNEL_WENDLAND) sweep(std::integral_constant<int, KERNEL_WENDLAND>());
+    else sweep(std::integral_constant<int, KERNEL_CUBIC>());
     if (err) atomicOr(s.err, err);
 }
 
@@ -1510,83 +1519,90 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
     const float im2_0 = (float)(1.0 / (d->mass[0] * d->mass[0]));
     const float im2_1 = (float)(1.0 / (d->mass[1] * d->mass[1]));
     const int NW = (int)S.NW;
-    for (uint32_t chunk = 0; chunk < nt; chunk += 64) {
-        const int ntc = (int)min(64u, nt - chunk);
-        const int G = 64 / ntc;
-        const int g = lane / ntc, tt = lane % ntc;
-        const bool target = g < G;
-        const uint32_t p = pbase + chunk + tt;
-        const bool fluid = target && (SK[p] >> 1) == KIND_FLUID;
-        const uint32_t ki = toff + chunk + tt;
-        const float4 Ai = SA[ki], Bi = SB[ki], Ci = SC[ki];
-        const ForceI32 I = force_target(K, Ai, Bi, Ci, im2_0, im2_1);
-        const int spi = Bi.w < 0.0f ? 1 : 0;
-        // all of the target's mask words at once (no chain of dependent loads); group g
-        // takes hits [lo, lo + cnt), starting in window c
-        const uint64_t *gm = s.masks + (size_t)p * kMaskSlots;
-        uint64_t mw[kCandWin];
-        uint32_t H = 0;
-#pragma unroll
-        for (int cc = 0; cc < kCandWin; cc++) {
-            mw[cc] = (fluid && cc < NW) ? gm[cc] : 0ull;
-            H += (uint32_t)__popcll(mw[cc]);
-        }
-        const uint32_t lo = (H * (uint32_t)g) / (uint32_t)G;
-        const uint32_t cnt = (H * (uint32_t)(g + 1)) / (uint32_t)G - lo;
-        int c = 0;
-        uint32_t pre = 0, before = 0;
-#pragma unroll
-        for (int cc = 0; cc < kCandWin; cc++) {
-            pre += (uint32_t)__popcll(mw[cc]);
-            if (pre <= lo) {
-                c = cc + 1;
-                before = pre;
+    // the chunk loop is compiled once per smoothing kernel, chosen per brick (a batch may
+    // mix kernels), so that the hit loop carries no branch on it
+    auto sweep = [&](auto kt) {
+        constexpr int KT = decltype(kt)::value;
+        for (uint32_t chunk = 0; chunk < nt; chunk += 64) {
+            const int ntc = (int)min(64u, nt - chunk);
+            const int G = 64 / ntc;
+            const int g = lane / ntc, tt = lane % ntc;
+            const bool target = g < G;
+            const uint32_t p = pbase + chunk + tt;
+            const bool fluid = target && (SK[p] >> 1) == KIND_FLUID;
+            const uint32_t ki = toff + chunk + tt;
+            const float4 Ai = SA[ki], Bi = SB[ki], Ci = SC[ki];
+            const ForceI32 I = force_target(K, Ai, Bi, Ci, im2_0, im2_1);
+            const int spi = Bi.w < 0.0f ? 1 : 0;
+            // all of the target's mask words at once (no chain of dependent loads); group g
+            // takes hits [lo, lo + cnt), starting in window c
+            const uint64_t *gm = s.masks + (size_t)p * kMaskSlots;
+            uint64_t mw[kCandWin];
+            uint32_t H = 0;
+    #pragma unroll
+            for (int cc = 0; cc < kCandWin; cc++) {
+                mw[cc] = (fluid && cc < NW) ? gm[cc] : 0ull;
+                H += (uint32_t)__popcll(mw[cc]);
+            }
+            const uint32_t lo = (H * (uint32_t)g) / (uint32_t)G;
+            const uint32_t cnt = (H * (uint32_t)(g + 1)) / (uint32_t)G - lo;
+            int c = 0;
+            uint32_t pre = 0, before = 0;
+    #pragma unroll
+            for (int cc = 0; cc < kCandWin; cc++) {
+                pre += (uint32_t)__popcll(mw[cc]);
+                if (pre <= lo) {
+                    c = cc + 1;
+                    before = pre;
+                }
+            }
+            uint64_t mc = 0, nxt = 0;  // bits of window c still to walk; window c + 1
+    #pragma unroll
+            for (int cc = 0; cc < kCandWin; cc++) {
+                if (cc == c) mc = mw[cc];
+                if (cc == c + 1) nxt = mw[cc];
+            }
+            if (cnt) mc = drop_low_bits(mc, lo - before);
+            Acc<float, KAHAN> F0, F1, F2, T0, T1, T2;
+            // per-lane trip count, two hits per trip (as in the density sweep)
+            auto next_k = [&]() {
+                while (mc == 0) {
+                    mc = nxt;
+                    ++c;
+                    nxt = c + 1 < NW ? gm[c + 1] : 0ull;
+                }
+                const int j = __builtin_ctzll(mc);
+                mc &= mc - 1;
+                return (uint32_t)tbl[w][c][j];
+            };
+            uint32_t kn = cnt ? next_k() : 0u;  // the next hit's index, decoded a hit ahead
+    #pragma unroll 2
+            for (uint32_t i = 0; i < cnt; i++) {
+                const uint32_t k = kn;
+                const float4 A = SA[k], B = SB[k], C = SC[k];
+                if (i + 1 < cnt) kn = next_k();
+                float f[3], n[3];
+                pair_force_f32<KT>(K, I, im2_0, im2_1, A, B, C, Ai.x - A.x, Ai.y - A.y, Ai.z - A.z,
+                               Bi.x - B.x, Bi.y - B.y, Bi.z - B.z, Ci.x + C.x, Ci.y + C.y,
+                               Ci.z + C.z, f, n);
+                F0.add(f[0]); F1.add(f[1]); F2.add(f[2]);
+                T0.add(n[0]); T1.add(n[1]); T2.add(n[2]);
+            }
+            const double f0 = group_total(F0.s, KAHAN ? F0.c : 0.0f, lane, ntc, G);
+            const double f1 = group_total(F1.s, KAHAN ? F1.c : 0.0f, lane, ntc, G);
+            const double f2 = group_total(F2.s, KAHAN ? F2.c : 0.0f, lane, ntc, G);
+            const double t0 = group_total(T0.s, KAHAN ? T0.c : 0.0f, lane, ntc, G);
+            const double t1 = group_total(T1.s, KAHAN ? T1.c : 0.0f, lane, ntc, G);
+            const double t2 = group_total(T2.s, KAHAN ? T2.c : 0.0f, lane, ntc, G);
+            if (target && g == 0) {
+                const double FF[3] = {fluid ? f0 : 0.0, fluid ? f1 : 0.0, fluid ? f2 : 0.0};
+                const double TT[3] = {fluid ? t0 : 0.0, fluid ? t1 : 0.0, fluid ? t2 : 0.0};
+                err |= force_finish<float>(s, d, p, spi, FF, TT);
             }
         }
-        uint64_t mc = 0, nxt = 0;  // bits of window c still to walk; window c + 1
-#pragma unroll
-        for (int cc = 0; cc < kCandWin; cc++) {
-            if (cc == c) mc = mw[cc];
-            if (cc == c + 1) nxt = mw[cc];
-        }
-        if (cnt) mc = drop_low_bits(mc, lo - before);
-        Acc<float, KAHAN> F0, F1, F2, T0, T1, T2;
-        // per-lane trip count, two hits per trip (as in the density sweep)
-        auto next_k = [&]() {
-            while (mc == 0) {
-                mc = nxt;
-                ++c;
-                nxt = c + 1 < NW ? gm[c + 1] : 0ull;
-            }
-            const int j = __builtin_ctzll(mc);
-            mc &= mc - 1;
-            return (uint32_t)tbl[w][c][j];
-        };
-        uint32_t kn = cnt ? next_k() : 0u;  // the next hit's index, decoded a hit ahead
-#pragma unroll 2
-        for (uint32_t i = 0; i < cnt; i++) {
-            const uint32_t k = kn;
-            const float4 A = SA[k], B = SB[k], C = SC[k];
-            if (i + 1 < cnt) kn = next_k();
-            float f[3], n[3];
-            pair_force_f32(K, I, im2_0, im2_1, A, B, C, Ai.x - A.x, Ai.y - A.y, Ai.z - A.z,
-                           Bi.x - B.x, Bi.y - B.y, Bi.z - B.z, Ci.x + C.x, Ci.y + C.y,
-                           Ci.z + C.z, f, n);
-            F0.add(f[0]); F1.add(f[1]); F2.add(f[2]);
-            T0.add(n[0]); T1.add(n[1]); T2.add(n[2]);
-        }
-        const double f0 = group_total(F0.s, KAHAN ? F0.c : 0.0f, lane, ntc, G);
-        const double f1 = group_total(F1.s, KAHAN ? F1.c : 0.0f, lane, ntc, G);
-        const double f2 = group_total(F2.s, KAHAN ? F2.c : 0.0f, lane, ntc, G);
-        const double t0 = group_total(T0.s, KAHAN ? T0.c : 0.0f, lane, ntc, G);
-        const double t1 = group_total(T1.s, KAHAN ? T1.c : 0.0f, lane, ntc, G);
-        const double t2 = group_total(T2.s, KAHAN ? T2.c : 0.0f, lane, ntc, G);
-        if (target && g == 0) {
-            const double FF[3] = {fluid ? f0 : 0.0, fluid ? f1 : 0.0, fluid ? f2 : 0.0};
-            const double TT[3] = {fluid ? t0 : 0.0, fluid ? t1 : 0.0, fluid ? t2 : 0.0};
-            err |= force_finish<float>(s, d, p, spi, FF, TT);
-        }
-    }
+    };
+    if (d->kernel == KERNEL_WENDLAND) sweep(std::integral_constant<int, KERNEL_WENDLAND>());
+    else sweep(std::integral_constant<int, KERNEL_CUBIC>());
     if (err) atomicOr(s.err, err);
 }
 
