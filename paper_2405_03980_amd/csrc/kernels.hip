@@ -424,8 +424,9 @@ __device__ __forceinline__ uint32_t density_finish(const DevState &s, const Inst
         double r2 = r * r;
         P = d->B * ((r2 * r2) * (r2 * r) - 1.0);
     }
-    double V = mi / rho;
-    double ir2 = 1.0 / (rho * rho);
+    const double irho = 1.0 / rho;
+    double V = mi * irho;
+    double ir2 = irho * irho;
     R *aux = (R *)s.aux + 4 * (size_t)p;
     aux[0] = (R)V;
     aux[1] = (R)(P * ir2);
@@ -545,7 +546,7 @@ __device__ __forceinline__ uint32_t force_finish(const DevState &s, const InstDe
 {
     R *acc = (R *)s.acc, *alpha = (R *)s.alpha;
     const uint32_t N = s.N;
-    const double im = 1.0 / d->mass[spi], iI = 1.0 / d->inertia[spi];
+    const double im = d->inv_mass[spi], iI = d->inv_inertia[spi];
     uint32_t err = 0;
     for (int a = 0; a < 3; a++) {
         double av = F[a] * im, al = T[a] * iI;
@@ -1032,10 +1033,11 @@ __device__ __forceinline__ void pair_force_f32(const ForceK<float> &k, const For
     const float gT = unl ? -k.sigT * mFk * (I.ir2 + ir2j) : 0.0f;
     const float gm = unl ? -k.Cl * W * (I.VS + C.w) : 0.0f;
     const float gv = I.ev * fmaxf(-B.w, 0.0f) * Fk;
-    const float u0 = v0 - (hs1 * r2 - hs2 * r1);
-    const float u1 = v1 - (hs2 * r0 - hs0 * r2);
-    const float u2 = v2 - (hs0 * r1 - hs1 * r0);
-    const float c0 = gm * v0 + gv * u0, c1 = gm * v1 + gv * u1, c2 = gm * v2 + gv * u2;
+    // gm v + gv (v - hs x r), regrouped as (gm + gv) v - gv (hs x r)
+    const float gmv = gm + gv;
+    const float c0 = gmv * v0 - gv * (hs1 * r2 - hs2 * r1);
+    const float c1 = gmv * v1 - gv * (hs2 * r0 - hs0 * r2);
+    const float c2 = gmv * v2 - gv * (hs0 * r1 - hs1 * r0);
     const float gh = gp + gT;
     f[0] = gh * r0 + c0;
     f[1] = gh * r1 + c1;

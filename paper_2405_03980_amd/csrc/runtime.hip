@@ -222,6 +222,8 @@ sph_status plan(int32_t n_inst, const sph_params *params, const int64_t *counts,
         for (int s = 0; s < 2; s++) {
             d.mass[s] = p->mass[s] > 0.0 ? p->mass[s] : dflt;
             d.inertia[s] = p->kappa_I * d.mass[s] * p->dx * p->dx;
+            d.inv_mass[s] = 1.0 / d.mass[s];
+            d.inv_inertia[s] = 1.0 / d.inertia[s];
         }
         d.rho0 = p->rho0;
         d.B = p->rho0 * p->c0 * p->c0 / p->gamma;

@@ -27,6 +27,7 @@ struct InstDesc {
     double wnorm;               // kernel normalisation constant
     double W0;                  // W(0)
     double mass[2], inertia[2]; // per species; inertia = kappa_I m dx^2
+    double inv_mass[2], inv_inertia[2];
     double rho0, B;             // Tait: P = B ((rho/rho0)^7 - 1)
     double eta, sigma_T, C_l;
     int32_t n[3], periodic[3];
