@@ -4,12 +4,17 @@
 //   k_keys     half kick + drift of each particle (walls: exact rotation), its cell in
 //              Morton order, and its slot in that cell (atomic histogram);
 //   k_scan_*   exclusive scan of the cell histogram -> cell_start (CSR of the cell list);
-//   k_scatter  counting-sort scatter;
+//   k_scatter  counting-sort scatter (and the ids in scatter order);
 //   k_reorder  orders each cell by particle id and moves the advanced state into the new
 //              cell-sorted order (the paper's periodic defragmentation, done every step);
-//   k_density  kernel-summed density, Tait EOS (Eq. 4) and the per-particle factors the
+//   density    kernel-summed density, Tait EOS (Eq. 4) and the per-particle factors the
 //              force sweep needs;
-//   k_force    pair forces of Eqs. 1-2 and the spin torques.
+//   force      pair forces of Eqs. 1-2 and the spin torques.
+// The density and force sweeps come in three forms: one thread per particle (k_density,
+// k_force; the FP64 path), and two that stage a 2x2x2-cell brick's neighbourhood in LDS
+// (FP32-mixed path, cell factor 1): target-major window tests (k_density_brick,
+// k_force_brick) and candidate-major ballot tests (k_density_cand, k_force_cand, the
+// default), both after k_brick_frames.
 // The closing half kick is folded into the next k_keys / k_reorder.
 #include <math.h>
 #include <type_traits>
@@ -695,7 +700,8 @@ __global__ void __launch_bounds__(64) k_brick_frames(DevState s)
     double sh[3];
     uint32_t beg = 0, cnt = 0;
     if (slot_cell(d, s.brick_xyz[brick], t, c, sh)) {
-        const uint32_t lin = (uint32_t)c[0] + (uint32_t)d->n[0] * ((uint32_t)c[1] + (uint32_t)d->n[1] * (uint32_t)c[2]);
+        const uint32_t lin = (uint32_t)c[0] +
+                             (uint32_t)d->n[0] * ((uint32_t)c[1] + (uint32_t)d->n[1] * (uint32_t)c[2]);
         const uint32_t r = s.rank_of_lin[d->cell_off + lin];
         beg = s.start[r];
         cnt = s.start[r + 1] - beg;
@@ -969,7 +975,8 @@ __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sq
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Single-precision W and F = -W'/r with the hardware square root and reciprocal.
-__device__ __forceinline__ void kernel_WF_fast(int kernel, float r2, float inv_h, float wnorm, float &W, float &F)
+__device__ __forceinline__ void kernel_WF_fast(int kernel, float r2, float inv_h, float wnorm, float &W,
+                                               float &F)
 {
     const float q = fast_sqrt(r2) * inv_h;
     const float ih2 = inv_h * inv_h;
@@ -1067,7 +1074,8 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_brick(DevState s)
     if (!F.ok) {
         if (has_cell) {
             const uint32_t nt = F.off[tslot + 1] - F.off[tslot];
-            for (uint32_t i = lane; i < nt; i += 64) err |= density_one<float, KAHAN>(s, d, F.begin[tslot] + i);
+            for (uint32_t i = lane; i < nt; i += 64)
+                err |= density_one<float, KAHAN>(s, d, F.begin[tslot] + i);
         }
         if (err) atomicOr(s.err, err);
         return;
@@ -1100,7 +1108,9 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_brick(DevState s)
             return wnorm * 0.25f * tt * tt * tt;
         };
         const bool rec_ok = masks_fit(F, ts, G);
-        uint64_t *rec = (rec_ok && active) ? s.masks + (size_t)(F.begin[tslot] + chunk + t) * kMaskSlots + g : nullptr;
+        uint64_t *rec = (rec_ok && active)
+                            ? s.masks + (size_t)(F.begin[tslot] + chunk + t) * kMaskSlots + g
+                            : nullptr;
         stencil_windows(F, win[w], ts, lane, active ? g : 0, G, rec_ok, false, rec,
             [&](uint32_t k, bool in_row) {
                 const float4 c = stage[k];
@@ -1353,7 +1363,8 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
     if (!F.ok) {
         if (has_cell) {
             const uint32_t nt = F.off[tslot + 1] - F.off[tslot];
-            for (uint32_t i = lane; i < nt; i += 64) err |= density_one<float, KAHAN>(s, d, F.begin[tslot] + i);
+            for (uint32_t i = lane; i < nt; i += 64)
+                err |= density_one<float, KAHAN>(s, d, F.begin[tslot] + i);
         }
         if (err) atomicOr(s.err, err);
         return;
@@ -1389,9 +1400,10 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
         constexpr int KT = decltype(kt)::value;
         for (uint32_t t0 = 0; t0 < nt; t0 += kListTargets) {
             const uint32_t ntc = min((uint32_t)kListTargets, nt - t0);
-            // test: one target at a time against every window; lane t collects target t's masks
+            // test: one target at a time against every window; lane t collects target t's
+            // masks
             uint32_t mlo[kCandWin], mhi[kCandWin];
-    #pragma unroll
+#pragma unroll
             for (int c = 0; c < kCandWin; c++) mlo[c] = mhi[c] = 0u;
             switch (S.NW) {
             case 1: test_targets<1>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
@@ -1410,7 +1422,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
             if ((uint32_t)lane < ntc) {
                 const uint32_t vs = stencil_self(S, toff + t0 + (uint32_t)lane);
                 const uint32_t keep = ~(1u << (vs & 31));
-    #pragma unroll
+#pragma unroll
                 for (int c = 0; c < kCandWin; c++) {
                     if ((vs >> 6) == (uint32_t)c) {
                         if (vs & 32) mhi[c] &= keep;
@@ -1420,7 +1432,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
             }
             if ((uint32_t)lane < ntc) {
                 uint64_t *gm = s.masks + (size_t)(pbase + t0 + lane) * kMaskSlots;
-    #pragma unroll
+#pragma unroll
                 for (int c = 0; c < kCandWin; c++) {
                     if (c < (int)S.NW) {
                         const uint64_t m = ((uint64_t)mhi[c] << 32) | mlo[c];
@@ -1443,8 +1455,8 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
             hit_share([&](int cc) { return mrow[cc]; }, act ? H : 0u, g, G, cnt, c, mc);
             const float4 me = stage[toff + t0 + tt];
             Acc<float, KAHAN> sw, su;
-            // the next hit's table and stage reads are issued before this hit's arithmetic, so
-            // the chain of dependent LDS reads overlaps it
+            // the next hit's table and stage reads are issued before this hit's arithmetic,
+            // so the chain of dependent LDS reads overlaps it
             auto next_hit = [&]() {
                 while (mc == 0) mc = mrow[++c];
                 const int j = __builtin_ctzll(mc);
@@ -1452,9 +1464,9 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
                 return stage[tbl[w][c][j]];
             };
             float4 q = cnt ? next_hit() : me;
-            // a per-lane trip count (lanes leave as they finish), two hits per trip so that the
-            // compensated sums alternate registers instead of being copied back each hit
-    #pragma unroll 2
+            // a per-lane trip count (lanes leave as they finish), two hits per trip so that
+            // the compensated sums alternate registers instead of being copied back each hit
+#pragma unroll 2
             for (uint32_t i = 0; i < cnt; i++) {
                 const float4 qc = q;
                 if (i + 1 < cnt) q = next_hit();
@@ -1541,7 +1553,7 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
             const uint64_t *gm = s.masks + (size_t)p * kMaskSlots;
             uint64_t mw[kCandWin];
             uint32_t H = 0;
-    #pragma unroll
+#pragma unroll
             for (int cc = 0; cc < kCandWin; cc++) {
                 mw[cc] = (fluid && cc < NW) ? gm[cc] : 0ull;
                 H += (uint32_t)__popcll(mw[cc]);
@@ -1550,7 +1562,7 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
             const uint32_t cnt = (H * (uint32_t)(g + 1)) / (uint32_t)G - lo;
             int c = 0;
             uint32_t pre = 0, before = 0;
-    #pragma unroll
+#pragma unroll
             for (int cc = 0; cc < kCandWin; cc++) {
                 pre += (uint32_t)__popcll(mw[cc]);
                 if (pre <= lo) {
@@ -1559,7 +1571,7 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
                 }
             }
             uint64_t mc = 0, nxt = 0;  // bits of window c still to walk; window c + 1
-    #pragma unroll
+#pragma unroll
             for (int cc = 0; cc < kCandWin; cc++) {
                 if (cc == c) mc = mw[cc];
                 if (cc == c + 1) nxt = mw[cc];
@@ -1578,7 +1590,7 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
                 return (uint32_t)tbl[w][c][j];
             };
             uint32_t kn = cnt ? next_k() : 0u;  // the next hit's index, decoded a hit ahead
-    #pragma unroll 2
+#pragma unroll 2
             for (uint32_t i = 0; i < cnt; i++) {
                 const uint32_t k = kn;
                 const float4 A = SA[k], B = SB[k], C = SC[k];
