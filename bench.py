@@ -48,7 +48,7 @@ BYTES_PER_PARTICLE = {
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--nz", type=int, default=184, help="cylinder resolution (184: 19.57M)")
     ap.add_argument("--fp64-steps", type=int, default=5)
