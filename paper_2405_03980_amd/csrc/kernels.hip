@@ -998,7 +998,7 @@ __device__ __forceinline__ void kernel_WF_fast(int kernel, float r2, float inv_h
 // Target-side factors of the staged FP32 pair terms (constant over a target's neighbours).
 struct ForceI32 {
     float m, Pr, ir2, VS;
-    float xs;  // 1 for the normal species, -1 for the viscous one: B.w * xs < 0 marks unlike
+    bool sp;   // viscous species
     float ev;  // -4 eta V for the viscous species, 0 for the other
 };
 
@@ -1014,14 +1014,14 @@ __device__ __forceinline__ ForceI32 force_target(const ForceK<float> &k, float4 
     I.Pr = A.w;
     I.ir2 = V * V * (sp ? im2_1 : im2_0);
     I.VS = C.w;
-    I.xs = sp ? -1.0f : 1.0f;
+    I.sp = sp;
     I.ev = sp ? -k.eta4 * V : 0.0f;
     return I;
 }
 
 // The same pair terms as pair_force from the staged neighbour (A, B, C as in the staging),
 // without branches on the species: the unlike terms are selected, the viscous-viscous one
-// vanishes through ev and max(-B.w, 0) (= V_j for a viscous neighbour, else 0).  KT fixes
+// vanishes through ev and V_j taken only for a viscous neighbour (B.w = -V_j).  KT fixes
 // the smoothing kernel at compile time (-1: the one in k).
 template <int KT = -1>
 __device__ __forceinline__ void pair_force_f32(const ForceK<float> &k, const ForceI32 &I, float im2_0,
@@ -1032,14 +1032,13 @@ __device__ __forceinline__ void pair_force_f32(const ForceK<float> &k, const For
     float W, Fk;
     kernel_WF_fast(KT < 0 ? k.kernel : KT, r0 * r0 + r1 * r1 + r2 * r2, k.inv_h, k.wnorm, W, Fk);
     const bool spj = B.w < 0.0f;
-    const bool unl = B.w * I.xs < 0.0f;
-    const float Vj = fabsf(B.w);
-    const float ir2j = Vj * Vj * (spj ? im2_1 : im2_0);
+    const bool unl = spj != I.sp;  // a scalar xor of lane masks
+    const float ir2j = B.w * B.w * (spj ? im2_1 : im2_0);
     const float mFk = I.m * (spj ? k.m1 : k.m0) * Fk;
     const float gp = mFk * (I.Pr + A.w);
     const float gT = unl ? -k.sigT * mFk * (I.ir2 + ir2j) : 0.0f;
     const float gm = unl ? -k.Cl * W * (I.VS + C.w) : 0.0f;
-    const float gv = I.ev * fmaxf(-B.w, 0.0f) * Fk;
+    const float gv = I.ev * (spj ? -B.w : 0.0f) * Fk;
     // gm v + gv (v - hs x r), regrouped as (gm + gv) v - gv (hs x r)
     const float gmv = gm + gv;
     const float c0 = gmv * v0 - gv * (hs1 * r2 - hs2 * r1);
