@@ -1454,21 +1454,17 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
             hit_share([&](int cc) { return mrow[cc]; }, act ? H : 0u, g, G, cnt, c, mc);
             const float4 me = stage[toff + t0 + tt];
             Acc<float, KAHAN> sw, su;
-            // the next hit's table and stage reads are issued before this hit's arithmetic,
-            // so the chain of dependent LDS reads overlaps it
             auto next_hit = [&]() {
                 while (mc == 0) mc = mrow[++c];
                 const int j = __builtin_ctzll(mc);
                 mc &= mc - 1;
                 return stage[tbl[w][c][j]];
             };
-            float4 q = cnt ? next_hit() : me;
             // a per-lane trip count (lanes leave as they finish), two hits per trip so that
             // the compensated sums alternate registers instead of being copied back each hit
 #pragma unroll 2
             for (uint32_t i = 0; i < cnt; i++) {
-                const float4 qc = q;
-                if (i + 1 < cnt) q = next_hit();
+                const float4 qc = next_hit();
                 const float d0 = me.x - qc.x, d1 = me.y - qc.y, d2 = me.z - qc.z;
                 const float W = kernel_W_fast(KT, d0 * d0 + d1 * d1 + d2 * d2, inv_h, wnorm);
                 sw.add(W);
@@ -1588,12 +1584,10 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
                 mc &= mc - 1;
                 return (uint32_t)tbl[w][c][j];
             };
-            uint32_t kn = cnt ? next_k() : 0u;  // the next hit's index, decoded a hit ahead
 #pragma unroll 2
             for (uint32_t i = 0; i < cnt; i++) {
-                const uint32_t k = kn;
+                const uint32_t k = next_k();
                 const float4 A = SA[k], B = SB[k], C = SC[k];
-                if (i + 1 < cnt) kn = next_k();
                 float f[3], n[3];
                 pair_force_f32<KT>(K, I, im2_0, im2_1, A, B, C, Ai.x - A.x, Ai.y - A.y, Ai.z - A.z,
                                Bi.x - B.x, Bi.y - B.y, Bi.z - B.z, Ci.x + C.x, Ci.y + C.y,
