@@ -202,10 +202,12 @@ __global__ void k_keys(DevState s, int mode, double kick, double dt)
     const uint32_t p = t.p;
     uint32_t err = 0;
     int kind = s.sk[s.cur][p] >> 1;
+    // only the new position is needed here (the spin and its acceleration are not loaded);
+    // k_reorder checks the advanced velocity and spin when it stores them
     double xo[3], vo[3], wo[3];
     advance<R>(s, d, kind, p, mode, kick, dt, xo, vo, wo);
     for (int a = 0; a < 3; a++)
-        if (!isfinite(xo[a]) || !isfinite(vo[a]) || !isfinite(wo[a])) err |= ERR_NONFINITE;
+        if (!isfinite(xo[a])) err |= ERR_NONFINITE;
     int c0 = cell_coord(d, 0, xo[0], err);
     int c1 = cell_coord(d, 1, xo[1], err);
     int c2 = cell_coord(d, 2, xo[2], err);
@@ -339,11 +341,14 @@ __global__ void k_reorder(DevState s, int mode, double kick, double dt)
     uint8_t skv = s.sk[cur][op];
     double xo[3], vo[3], wo[3];
     advance<R>(s, d, skv >> 1, op, mode, kick, dt, xo, vo, wo);
+    bool finite = true;
     for (int a = 0; a < 3; a++) {
         s.x[nxt][a * N + dst] = xo[a];
         s.v[nxt][a * N + dst] = vo[a];
         s.w[nxt][a * N + dst] = wo[a];
+        finite = finite && isfinite(vo[a]) && isfinite(wo[a]);
     }
+    if (!finite) atomicOr(s.err, (uint32_t)ERR_NONFINITE);
     s.id[nxt][dst] = myid;
     s.sk[nxt][dst] = skv;
     s.pcell[dst] = c;

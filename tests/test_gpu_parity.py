@@ -301,6 +301,22 @@ def test_nonfinite_input_is_reported():
     s.close()
 
 
+@pytest.mark.parametrize("prec", [FP64, MIXED])
+def test_nonfinite_spin_of_a_lone_particle_is_reported(prec):
+    """A particle without neighbours never reaches the pair sweeps, so a NaN spin can only
+    be caught where the state is stored (the reorder check)."""
+    x = np.array([[0.2, 0.7], [0.5, 0.5], [0.5, 0.5]])
+    om = np.array([[0.0, np.nan], [0.0, 0.0], [0.0, 0.0]])
+    p = I.base_params(I.KERNEL_WENDLAND_C2, I.GEOM_OPEN, 0.05, [0, 0, 0], [1, 1, 1], 1.0)
+    from paper_2405_03980_amd import sim as S
+    s = S.Simulation(p, 2, precision=prec)
+    s.init(x, np.zeros((3, 2)), om, np.zeros(2, np.uint8), np.zeros(2, np.uint8))
+    with pytest.raises(L.SphError) as e:
+        s.sync()
+    assert e.value.status == L.E_NONFINITE
+    s.close()
+
+
 def test_domain_exit_is_reported():
     w = I.make_cluster(5)
     w.v[0, 0] = 1e4  # leaves the open grid in one step
