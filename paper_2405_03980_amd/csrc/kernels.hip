@@ -1533,29 +1533,40 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
     const float im2_0 = (float)(1.0 / (d->mass[0] * d->mass[0]));
     const float im2_1 = (float)(1.0 / (d->mass[1] * d->mass[1]));
     const int NW = (int)S.NW;
-    // the chunk loop is compiled once per smoothing kernel, chosen per brick (a batch may
-    // mix kernels), so that the hit loop carries no branch on it
+    // Per block of up to 64 targets: wall targets get zero force and torque directly, and the
+    // fluid targets share the lanes as (target, group g of G), so walls take no lanes.
+    // Compiled once per smoothing kernel, chosen per brick (a batch may mix kernels), so
+    // that the hit loop carries no branch on it.
     auto sweep = [&](auto kt) {
         constexpr int KT = decltype(kt)::value;
-        for (uint32_t chunk = 0; chunk < nt; chunk += 64) {
-            const int ntc = (int)min(64u, nt - chunk);
-            const int G = 64 / ntc;
-            const int g = lane / ntc, tt = lane % ntc;
+        for (uint32_t t0 = 0; t0 < nt; t0 += 64) {
+            const uint32_t nb = min(64u, nt - t0);
+            uint32_t sk_t = 0;
+            if ((uint32_t)lane < nb) sk_t = SK[pbase + t0 + lane];
+            const bool fluid_t = (uint32_t)lane < nb && (sk_t >> 1) == KIND_FLUID;
+            const uint64_t M = __ballot(fluid_t);
+            if ((uint32_t)lane < nb && !fluid_t) {
+                const double z[3] = {0.0, 0.0, 0.0};
+                err |= force_finish<float>(s, d, pbase + t0 + lane, sk_t & 1, z, z);
+            }
+            if (M == 0) continue;
+            const int n = __popcll(M);
+            const int G = 64 / n;
+            const int g = lane / n;
             const bool target = g < G;
-            const uint32_t p = pbase + chunk + tt;
-            const bool fluid = target && (SK[p] >> 1) == KIND_FLUID;
-            const uint32_t ki = toff + chunk + tt;
+            const uint32_t t = (uint32_t)__builtin_ctzll(drop_low_bits(M, (uint32_t)(lane % n)));
+            const uint32_t p = pbase + t0 + t;
+            const uint32_t ki = toff + t0 + t;
             const float4 Ai = SA[ki], Bi = SB[ki], Ci = SC[ki];
             const ForceI32 I = force_target(K, Ai, Bi, Ci, im2_0, im2_1);
-            const int spi = Bi.w < 0.0f ? 1 : 0;
             // all of the target's mask words at once (no chain of dependent loads); group g
-            // takes hits [lo, lo + cnt), starting in window c
+            // takes hits [lo, lo + cnt) in list order, starting in window c
             const uint64_t *gm = s.masks + (size_t)p * kMaskSlots;
             uint64_t mw[kCandWin];
             uint32_t H = 0;
 #pragma unroll
             for (int cc = 0; cc < kCandWin; cc++) {
-                mw[cc] = (fluid && cc < NW) ? gm[cc] : 0ull;
+                mw[cc] = (target && cc < NW) ? gm[cc] : 0ull;
                 H += (uint32_t)__popcll(mw[cc]);
             }
             const uint32_t lo = (H * (uint32_t)g) / (uint32_t)G;
@@ -1578,7 +1589,6 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
             }
             if (cnt) mc = drop_low_bits(mc, lo - before);
             Acc<float, KAHAN> F0, F1, F2, T0, T1, T2;
-            // per-lane trip count, two hits per trip (as in the density sweep)
             auto next_k = [&]() {
                 while (mc == 0) {
                     mc = nxt;
@@ -1589,27 +1599,28 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
                 mc &= mc - 1;
                 return (uint32_t)tbl[w][c][j];
             };
+            // per-lane trip count, two hits per trip (as in the density sweep)
 #pragma unroll 2
             for (uint32_t i = 0; i < cnt; i++) {
                 const uint32_t k = next_k();
                 const float4 A = SA[k], B = SB[k], C = SC[k];
-                float f[3], n[3];
+                float f[3], nn[3];
                 pair_force_f32<KT>(K, I, im2_0, im2_1, A, B, C, Ai.x - A.x, Ai.y - A.y, Ai.z - A.z,
-                               Bi.x - B.x, Bi.y - B.y, Bi.z - B.z, Ci.x + C.x, Ci.y + C.y,
-                               Ci.z + C.z, f, n);
+                                   Bi.x - B.x, Bi.y - B.y, Bi.z - B.z, Ci.x + C.x, Ci.y + C.y,
+                                   Ci.z + C.z, f, nn);
                 F0.add(f[0]); F1.add(f[1]); F2.add(f[2]);
-                T0.add(n[0]); T1.add(n[1]); T2.add(n[2]);
+                T0.add(nn[0]); T1.add(nn[1]); T2.add(nn[2]);
             }
-            const double f0 = group_total(F0.s, KAHAN ? F0.c : 0.0f, lane, ntc, G);
-            const double f1 = group_total(F1.s, KAHAN ? F1.c : 0.0f, lane, ntc, G);
-            const double f2 = group_total(F2.s, KAHAN ? F2.c : 0.0f, lane, ntc, G);
-            const double t0 = group_total(T0.s, KAHAN ? T0.c : 0.0f, lane, ntc, G);
-            const double t1 = group_total(T1.s, KAHAN ? T1.c : 0.0f, lane, ntc, G);
-            const double t2 = group_total(T2.s, KAHAN ? T2.c : 0.0f, lane, ntc, G);
+            const double f0 = group_total(F0.s, KAHAN ? F0.c : 0.0f, lane, n, G);
+            const double f1 = group_total(F1.s, KAHAN ? F1.c : 0.0f, lane, n, G);
+            const double f2 = group_total(F2.s, KAHAN ? F2.c : 0.0f, lane, n, G);
+            const double q0 = group_total(T0.s, KAHAN ? T0.c : 0.0f, lane, n, G);
+            const double q1 = group_total(T1.s, KAHAN ? T1.c : 0.0f, lane, n, G);
+            const double q2 = group_total(T2.s, KAHAN ? T2.c : 0.0f, lane, n, G);
             if (target && g == 0) {
-                const double FF[3] = {fluid ? f0 : 0.0, fluid ? f1 : 0.0, fluid ? f2 : 0.0};
-                const double TT[3] = {fluid ? t0 : 0.0, fluid ? t1 : 0.0, fluid ? t2 : 0.0};
-                err |= force_finish<float>(s, d, p, spi, FF, TT);
+                const double FF[3] = {f0, f1, f2};
+                const double TT[3] = {q0, q1, q2};
+                err |= force_finish<float>(s, d, p, I.sp ? 1 : 0, FF, TT);
             }
         }
     };
