@@ -1327,20 +1327,27 @@ __device__ __forceinline__ float kernel_W_fast(int kernel, float r2, float inv_h
 // Ballot tests of targets kbase .. kbase + ntc - 1 (staged indices) against the first NWc
 // candidate windows, NWc fixed at compile time so that the windows need no branch per
 // target.  Lane t ORs target t's masks into mlo/mhi (low and high halves).
+// The test is |c - t|^2 < cut2 expanded as |c|^2 - 2 c.t < cut2 - |t|^2, with the
+// candidate's -2c (px, py, pz) and |c|^2 (cc) precomputed: three FMAs and a compare per
+// target and window.  Positions are relative to the brick centre (|c|^2 <= 48 h^2), so the
+// expanded form can misjudge only pairs within a few 1e-6 of the support radius, where W
+// and F are below 1e-17 of their scale.
 template <int NWc>
-__device__ __forceinline__ void test_targets(const float4 *stage, const float *cx, const float *cy,
-                                             const float *cz, uint32_t kbase, uint32_t ntc,
-                                             float cut2, int lane, uint32_t *mlo, uint32_t *mhi)
+__device__ __forceinline__ void test_targets(const float4 *stage, const float *px, const float *py,
+                                             const float *pz, const float *cc, uint32_t kbase,
+                                             uint32_t ntc, float cut2, int lane, uint32_t *mlo,
+                                             uint32_t *mhi)
 {
     for (uint32_t t = 0; t < ntc; t++) {
         const float4 T = stage[kbase + t];
+        const float thr = cut2 - (T.x * T.x + T.y * T.y + T.z * T.z);
         uint32_t mine = (uint32_t)lane == t ? ~0u : 0u;
         asm volatile("" : "+v"(mine));  // an opaque lane mask, so that the updates below
                                         // stay one and-or instead of becoming selects
 #pragma unroll
         for (int c = 0; c < NWc; c++) {
-            const float d0 = cx[c] - T.x, d1 = cy[c] - T.y, d2 = cz[c] - T.z;
-            const uint64_t m = __ballot(d0 * d0 + d1 * d1 + d2 * d2 < cut2);
+            const float e = fmaf(pz[c], T.z, fmaf(py[c], T.y, fmaf(px[c], T.x, cc[c])));
+            const uint64_t m = __ballot(e < thr);
             mlo[c] |= mine & (uint32_t)m;
             mhi[c] |= mine & (uint32_t)(m >> 32);
         }
@@ -1386,15 +1393,17 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
         if (err) atomicOr(s.err, err);
         return;
     }
-    float cx[kCandWin], cy[kCandWin], cz[kCandWin];
+    float px[kCandWin], py[kCandWin], pz[kCandWin], cc[kCandWin];
 #pragma unroll
     for (int c = 0; c < kCandWin; c++) {
-        cx[c] = cy[c] = cz[c] = __builtin_inff();  // never within reach
+        px[c] = py[c] = pz[c] = 0.0f;
+        cc[c] = __builtin_inff();  // never within reach
         if (c < (int)S.NW && 64u * (uint32_t)c + (uint32_t)lane < S.C) {
             const float4 q = stage[tbl[w][c][lane]];
-            cx[c] = q.x;
-            cy[c] = q.y;
-            cz[c] = q.z;
+            px[c] = -2.0f * q.x;
+            py[c] = -2.0f * q.y;
+            pz[c] = -2.0f * q.z;
+            cc[c] = q.x * q.x + q.y * q.y + q.z * q.z;
         }
     }
     const float cut2 = (float)d->cut2, inv_h = (float)d->inv_h, wnorm = (float)d->wnorm;
@@ -1410,16 +1419,16 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
 #pragma unroll
             for (int c = 0; c < kCandWin; c++) mlo[c] = mhi[c] = 0u;
             switch (S.NW) {
-            case 1: test_targets<1>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-            case 2: test_targets<2>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-            case 3: test_targets<3>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-            case 4: test_targets<4>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-            case 5: test_targets<5>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-            case 6: test_targets<6>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-            case 7: test_targets<7>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-            case 8: test_targets<8>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-            case 9: test_targets<9>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-            default: test_targets<10>(stage, cx, cy, cz, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+            case 1: test_targets<1>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+            case 2: test_targets<2>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+            case 3: test_targets<3>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+            case 4: test_targets<4>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+            case 5: test_targets<5>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+            case 6: test_targets<6>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+            case 7: test_targets<7>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+            case 8: test_targets<8>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+            case 9: test_targets<9>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+            default: test_targets<10>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mlo, mhi); break;
             }
             static_assert(kCandWin == 10, "one case per window count");
             // a target is not its own neighbour: its lane clears the bit of its list position
