@@ -217,9 +217,9 @@ def main():
     def run(precision, steps, warmup, tuning):
         tun, cf = tuning
         s = S.Simulation(dict(w.params, cell_factor=cf), w.n, precision=precision)
-        s.init(w.x, w.v, w.omega, w.species, w.kind)
         if tun:
             s.set_tuning(**tun)
+        s.init(w.x, w.v, w.omega, w.species, w.kind)
         s.step(1e-4, w.Omega, warmup)
         s.sync()
         torch.cuda.synchronize()

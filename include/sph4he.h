@@ -107,10 +107,10 @@ typedef struct {
     int32_t use_graph;      /* 1: replay steps from a captured hipGraph (needs a non-null */
                             /* stream); 0: launch eagerly; -1: keep                        */
     int32_t sweep;          /* FP32-mixed density/force sweeps: 1 one thread per particle; */
-                            /* 2 one workgroup per 2x2x2-cell brick staged in LDS, lanes   */
-                            /* over targets; 3 (default) the same bricks, lanes over       */
-                            /* candidates for the neighbour test; 2 and 3 need cell_factor */
-                            /* 1 on every instance (else 1 is used); 0: keep               */
+                            /* 3 (default) one workgroup per 2x2x2-cell brick staged in    */
+                            /* LDS, lanes over candidates for the neighbour test; needs    */
+                            /* cell_factor 1 on every instance (else 1 is used); 0: keep;  */
+                            /* any other value is SPH_E_INVALID                            */
 } sph_tuning;
 
 typedef struct sph_sim sph_sim;      /* one SPH instance (opaque, host memory)            */

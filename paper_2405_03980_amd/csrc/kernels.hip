@@ -10,11 +10,10 @@
 //   density    kernel-summed density, Tait EOS (Eq. 4) and the per-particle factors the
 //              force sweep needs;
 //   force      pair forces of Eqs. 1-2 and the spin torques.
-// The density and force sweeps come in three forms: one thread per particle (k_density,
-// k_force; the FP64 path), and two that stage a 2x2x2-cell brick's neighbourhood in LDS
-// (FP32-mixed path, cell factor 1): target-major window tests (k_density_brick,
-// k_force_brick) and candidate-major ballot tests (k_density_cand, k_force_cand, the
-// default), both after k_brick_frames.
+// The density and force sweeps come in two forms: one thread per particle (k_density,
+// k_force; the FP64 path), and one that stages a 2x2x2-cell brick's neighbourhood in LDS
+// and tests candidates with wave ballots (k_density_cand, k_force_cand, after
+// k_brick_frames; the FP32-mixed default with cell factor 1).
 // The closing half kick is folded into the next k_keys / k_reorder.
 #include <math.h>
 #include <type_traits>
@@ -643,20 +642,13 @@ __global__ void k_force(DevState s)
 // One workgroup per brick of 2x2x2 cells (edge >= 2h each).  The 4x4x4 cells around the
 // brick (its neighbourhood, periodic images shifted into the brick's frame) are staged in
 // LDS in slot order, x fastest, so the 27-cell stencil of a target cell is 9 contiguous
-// runs ("rows").  Wave w serves brick cell w: its lanes are (target, candidate group)
-// pairs, group g taking every G-th candidate of each row, so lanes of a group read the same
-// LDS word, and the G partial sums of a target are combined at the end in a fixed order.
-//
-// Each lane walks its trips in windows of at most 64: it first tests the window's
-// candidates into a 64-bit hit mask, then evaluates the pair terms of the set bits only, so
-// the pair arithmetic runs on compacted neighbours.  A per-wave table maps a bit back to
-// its candidate.  Positions are staged in single precision relative to the brick centre
-// (FP32-mixed path); neighbourhoods too large to stage fall back to the per-particle code.
+// runs ("rows").  Wave w serves brick cell w.  Positions are staged in single precision
+// relative to the brick centre (FP32-mixed path); neighbourhoods too large to stage fall
+// back to the per-particle code.
 
 constexpr int kBrickThreads = 512;
 constexpr int kStageDensity = 2048;
 constexpr int kStageForce = 1408;
-constexpr int kMergeWin = 4;  // windows whose hits a lane processes as one stream
 
 struct BrickFrame {
     uint32_t begin[64];   // sorted index of each slot's first particle
@@ -666,11 +658,19 @@ struct BrickFrame {
     uint32_t ok;          // 0: too many particles to stage (per-thread fallback)
 };
 
-// Per wave of the target-major sweeps, for the (up to kMergeWin) windows being processed:
-// candidate of bit j of window c = win[c][j] + g + G * j.
-typedef int16_t WindowTable[kBrickThreads / 64][kMergeWin][64];
-
 __device__ __forceinline__ int slot_index(int x, int y, int z) { return x + 4 * (y + 4 * z); }
+
+// Hands LDS data written by some lanes of a wave to other lanes of the same wave.  A bare
+// wave barrier orders execution only: the compiler may still move or overlap the LDS
+// accesses around it.  Here the fences keep LDS accesses on their side, and the wave waits
+// until its own LDS writes are complete (lgkmcnt 0; vector memory counters untouched).
+__device__ __forceinline__ void wave_lds_handoff()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0), vmcnt(63), expcnt(7)
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Slot t (x + 4y + 16z over the 4x4x4 neighbourhood) of brick bxyz: its cell (wrapped on
 // periodic axes, with the image shift in sh) and whether the cell lies in the grid.
@@ -813,8 +813,9 @@ constexpr int kSlotThreads = kBrickThreads / 64;
 static_assert(kSlotThreads * 64 == kBrickThreads, "staging assigns whole slots to threads");
 
 // Stages the positions of the brick's neighbourhood particles relative to the brick centre
-// (FP64 difference, then FP32) and their species.
-__device__ __forceinline__ void stage_density(const DevState &s, const BrickFrame &F, float4 *stage)
+// in units of h (FP64 difference and scaling, then FP32) and their species.
+__device__ __forceinline__ void stage_density(const DevState &s, const BrickFrame &F, double ih,
+                                              float4 *stage)
 {
     const uint32_t N = s.N;
     const double *X = s.x[s.cur];
@@ -834,9 +835,9 @@ __device__ __forceinline__ void stage_density(const DevState &s, const BrickFram
             const uint32_t k = k0 + (uint32_t)(u * kSlotThreads);
             if (k >= cnt) break;
             float4 v;
-            v.x = (float)((px[u][0] + F.shift[sl][0]) - F.origin[0]);
-            v.y = (float)((px[u][1] + F.shift[sl][1]) - F.origin[1]);
-            v.z = (float)((px[u][2] + F.shift[sl][2]) - F.origin[2]);
+            v.x = (float)(((px[u][0] + F.shift[sl][0]) - F.origin[0]) * ih);
+            v.y = (float)(((px[u][1] + F.shift[sl][1]) - F.origin[1]) * ih);
+            v.z = (float)(((px[u][2] + F.shift[sl][2]) - F.origin[2]) * ih);
             v.w = (float)(sk[u] & 1);
             stage[off + k] = v;
         }
@@ -846,10 +847,12 @@ __device__ __forceinline__ void stage_density(const DevState &s, const BrickFram
 // Stages what the force sweep reads of the brick's M neighbourhood particles: position
 // relative to the brick centre and P/rho^2; velocity relative to vref and V (negative for
 // the viscous species); half the spin (exact, so (w_i + w_j)/2 takes one add) and V/S.
-// Each thread takes up to three particles spread evenly over the neighbourhood (the
-// heavier force staging prefers this to whole slots).
+// Positions and velocities are in units of h (ih = 1/h, applied in FP64).  Each thread
+// takes up to three particles spread evenly over the neighbourhood (the heavier force
+// staging prefers this to whole slots).
 __device__ __forceinline__ void stage_force(const DevState &s, const BrickFrame &F, uint32_t M,
-                                            const double *vref, float4 *SA, float4 *SB, float4 *SC)
+                                            const double *vref, double ih, float4 *SA, float4 *SB,
+                                            float4 *SC)
 {
     const uint32_t N = s.N;
     const int cur = s.cur;
@@ -880,352 +883,154 @@ __device__ __forceinline__ void stage_force(const DevState &s, const BrickFrame 
         for (int u = 0; u < 3; u++) {
             if (kk[u] >= M) break;
             const uint32_t k = kk[u];
-            SA[k] = make_float4((float)((px[u][0] + F.shift[sl[u]][0]) - F.origin[0]),
-                                (float)((px[u][1] + F.shift[sl[u]][1]) - F.origin[1]),
-                                (float)((px[u][2] + F.shift[sl[u]][2]) - F.origin[2]), aq[u].y);
-            SB[k] = make_float4((float)(pv[u][0] - vref[0]), (float)(pv[u][1] - vref[1]),
-                                (float)(pv[u][2] - vref[2]), (sk[u] & 1) ? -aq[u].x : aq[u].x);
+            SA[k] = make_float4((float)(((px[u][0] + F.shift[sl[u]][0]) - F.origin[0]) * ih),
+                                (float)(((px[u][1] + F.shift[sl[u]][1]) - F.origin[1]) * ih),
+                                (float)(((px[u][2] + F.shift[sl[u]][2]) - F.origin[2]) * ih), aq[u].y);
+            SB[k] = make_float4((float)((pv[u][0] - vref[0]) * ih), (float)((pv[u][1] - vref[1]) * ih),
+                                (float)((pv[u][2] - vref[2]) * ih), (sk[u] & 1) ? -aq[u].x : aq[u].x);
             SC[k] = make_float4((float)(0.5 * pw[u][0]), (float)(0.5 * pw[u][1]), (float)(0.5 * pw[u][2]),
                                 aq[u].w);
         }
     }
 }
 
-// Trips of the stencil walk of the wave's target cell (rows split over G groups) and
-// whether the masks of all its windows fit the per-particle mask slots.
-__device__ __forceinline__ bool masks_fit(const BrickFrame &F, const int ts[3], int G)
-{
-    uint32_t T = 0;
-    for (int r = 0; r < 9; r++) {
-        const int s0 = slot_index(ts[0] - 1, ts[1] - 1 + (r % 3), ts[2] - 1 + (r / 3));
-        T += (F.off[s0 + 3] - F.off[s0] + (uint32_t)G - 1) / (uint32_t)G;
-    }
-    return (uint32_t)G * ((T + 63) / 64) <= (uint32_t)kMaskSlots;
-}
-
-// Walks the stencil of the wave's target cell in windows of <= 64 trips.  Per window each
-// lane builds a 64-bit hit mask, bit t = trip t, either by test(k, in_row) (when in_row is
-// false, the group's last trip ran past its row, k is clamped into the row and the test
-// must return false) or, when `replay`, by loading the mask recorded by an earlier walk
-// from rec[window * G].  When `record`, the mask is stored to rec[window * G].  After every
-// kMergeWin windows (and at the end) each lane calls body(k) for all hits of those windows
-// as one stream, so the wave waits for the lane with the most hits over several windows
-// rather than per window.  All lanes execute the same window and trip sequence.
-template <class Test, class Body>
-__device__ __forceinline__ void stencil_windows(const BrickFrame &F, int16_t (*win)[64], const int ts[3],
-                                                int lane, int g, int G, bool record, bool replay,
-                                                uint64_t *rec, Test &&test, Body &&body)
-{
-    int r = 0;          // current row (visiting order below)
-    uint32_t done = 0;  // trips of row r already walked
-    int wi = 0;         // window index
-    while (r < 9) {
-        uint64_t m[kMergeWin];
-        int nw = 0;
-        for (; nw < kMergeWin && r < 9; nw++, wi++) {
-            uint64_t tm = 0;
-            int W = 0;
-            while (r < 9 && W < 64) {
-                // rows in Latin-square order: every three consecutive rows cover all three
-                // z layers and all three y offsets, so each window holds a similar share of
-                // every target's neighbours whatever its position in the cell
-                const int dz = r % 3, dy = (r % 3 + r / 3) % 3;
-                const int s0 = slot_index(ts[0] - 1, ts[1] - 1 + dy, ts[2] - 1 + dz);
-                const uint32_t b = F.off[s0], e = F.off[s0 + 3];
-                const uint32_t trips = (e - b + (uint32_t)G - 1) / (uint32_t)G;
-                const uint32_t take = min(trips - done, (uint32_t)(64 - W));
-                if (lane >= W && lane < W + (int)take)
-                    win[nw][lane] = (int16_t)((int32_t)(b + (uint32_t)G * done) - G * W);
-                if (!replay) {
-                    const uint32_t kb = b + (uint32_t)g + (uint32_t)G * done;
-#pragma unroll 4
-                    for (uint32_t t = 0; t < take; t++) {
-                        const uint32_t k = kb + (uint32_t)G * t;
-                        const uint64_t bit = test(min(k, e - 1), k < e) ? 1ull : 0ull;
-                        tm |= bit << (W + (int)t);
-                    }
-                }
-                W += (int)take;
-                done += take;
-                if (done == trips) { r++; done = 0; }
-            }
-            uint64_t mask;
-            if (replay) {
-                mask = rec ? rec[wi * G] : 0ull;
-            } else {
-                mask = tm;
-                if (record && rec) rec[wi * G] = mask;
-            }
-            m[nw] = mask;
-        }
-        __builtin_amdgcn_wave_barrier();
-        // one stream over the collected windows: c is the window of the remaining bits mc
-        int c = 0;
-        uint64_t mc = m[0];
-        while (true) {
-            while (mc == 0 && c + 1 < nw) {
-                c++;
-                mc = c == 1 ? m[1] : (c == 2 ? m[2] : m[3]);
-            }
-            if (mc == 0) break;
-            const int j = __builtin_ctzll(mc);
-            mc &= mc - 1;
-            body((uint32_t)((int32_t)win[c][j] + g + G * j));
-        }
-        __builtin_amdgcn_wave_barrier();
-    }
-}
-
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Single-precision W and F = -W'/r with the hardware square root and reciprocal.
-__device__ __forceinline__ void kernel_WF_fast(int kernel, float r2, float inv_h, float wnorm, float &W,
-                                               float &F)
+// ---------------------------------------------------------- staged FP32 pair terms ---
+// The brick sweeps stage positions and velocities in units of h (r_s = r/h, v_s = v/h), so
+// that q = |r_s|.  The kernels enter through their shapes: W = wnorm What(q) and
+// F = -W'/r = wnorm cF Fhat(q) / h^2, cF = 5 for Wendland C2 (What = t^4 (2q + 1),
+// Fhat = t^3, t = 1 - q/2) and 1 for the cubic spline (Sec. 2.2 kernels).  The constant
+// factors go into per-brick and per-target coefficients, once.
+
+// What(q) alone (density sweep), q = sqrt(r2s).
+template <int KT>
+__device__ __forceinline__ float shape_W(float r2s)
 {
-    const float q = fast_sqrt(r2) * inv_h;
-    const float ih2 = inv_h * inv_h;
-    if (kernel == KERNEL_WENDLAND) {
+    const float q = fast_sqrt(r2s);
+    if (KT == KERNEL_WENDLAND) {
+        const float t = 1.0f - 0.5f * q;
+        const float t2 = t * t;
+        return t2 * t2 * (2.0f * q + 1.0f);
+    }
+    if (q < 1.0f) return 1.0f - 1.5f * q * q + 0.75f * q * q * q;
+    const float t = 2.0f - q;
+    return 0.25f * t * t * t;
+}
+
+// What(q) and Fhat(q) (force sweep), q = sqrt(r2s).
+template <int KT>
+__device__ __forceinline__ void shape_WF(float r2s, float &W, float &F)
+{
+    const float q = fast_sqrt(r2s);
+    if (KT == KERNEL_WENDLAND) {
         const float t = 1.0f - 0.5f * q;
         const float t3 = t * t * t;
-        W = wnorm * t3 * t * (2.0f * q + 1.0f);
-        F = 5.0f * wnorm * t3 * ih2;
+        F = t3;
+        W = t3 * t * (2.0f * q + 1.0f);
     } else if (q < 1.0f) {
-        W = wnorm * (1.0f - 1.5f * q * q + 0.75f * q * q * q);
-        F = wnorm * (3.0f - 2.25f * q) * ih2;
+        W = 1.0f - 1.5f * q * q + 0.75f * q * q * q;
+        F = 3.0f - 2.25f * q;
     } else {
         const float t = 2.0f - q;
-        W = wnorm * 0.25f * t * t * t;
-        F = wnorm * 0.75f * t * t * ih2 * fast_rcp(q);
+        W = 0.25f * t * t * t;
+        F = 0.75f * t * t * fast_rcp(q);
     }
 }
 
-// Target-side factors of the staged FP32 pair terms (constant over a target's neighbours).
-struct ForceI32 {
-    float m, Pr, ir2, VS;
-    bool sp;   // viscous species
-    float ev;  // -4 eta V for the viscous species, 0 for the other
+// Per-brick coefficients of the staged force terms.  With r = h r_s and v = h v_s every
+// coefficient that multiplies r_s or v_s carries one factor h, so the force comes out in
+// true units and the accumulated torque n' gives the true one as -(h/2) n'.
+struct PairK {
+    float kM;        // h m0^2 F / Fhat = m0^2 wnorm cF / h
+    float mu1;       // m1 / m0
+    float ks0, ks1;  // -sigma_T / m_s^2, so -sigma_T / rho_j^2 = ks_j V_j^2
+    float kC;        // -C_l h wnorm
+    float ke;        // -4 eta / (m0 m1)
+    __device__ explicit PairK(const InstDesc *d)
+    {
+        const double cF = d->kernel == KERNEL_WENDLAND ? 5.0 : 1.0;
+        kM = (float)(d->mass[0] * d->mass[0] * d->wnorm * cF * d->inv_h);
+        mu1 = (float)(d->mass[1] / d->mass[0]);
+        ks0 = (float)(-d->sigma_T / (d->mass[0] * d->mass[0]));
+        ks1 = (float)(-d->sigma_T / (d->mass[1] * d->mass[1]));
+        kC = (float)(-d->C_l * d->h * d->wnorm);
+        ke = (float)(-4.0 * d->eta / (d->mass[0] * d->mass[1]));
+    }
 };
 
-// Target-side factors from the target's own staged values (SA.w = P/rho^2, SB.w = V with the
+// Target-side factors, from the target's staged values (SA.w = P/rho^2, SB.w = V with the
 // sign of the species, SC.w = V/S).
-__device__ __forceinline__ ForceI32 force_target(const ForceK<float> &k, float4 A, float4 B,
-                                                 float4 C, float im2_0, float im2_1)
+struct PairI {
+    float kM;   // kM m_i / m0
+    float Pr;   // P_i / rho_i^2
+    float sT;   // -sigma_T / rho_i^2
+    float cVS;  // kC V_i / S_i
+    float ev;   // viscous target: ke V_i m0 / m_i; 0 for the other species
+    bool sp;    // viscous species
+};
+
+__device__ __forceinline__ PairI pair_target(const PairK &k, float4 A, float4 B, float4 C)
 {
-    ForceI32 I;
+    PairI I;
     const bool sp = B.w < 0.0f;
     const float V = fabsf(B.w);
-    I.m = sp ? k.m1 : k.m0;
+    I.kM = sp ? k.kM * k.mu1 : k.kM;
     I.Pr = A.w;
-    I.ir2 = V * V * (sp ? im2_1 : im2_0);
-    I.VS = C.w;
+    I.sT = V * V * (sp ? k.ks1 : k.ks0);
+    I.cVS = k.kC * C.w;
+    I.ev = sp ? k.ke * V / k.mu1 : 0.0f;
     I.sp = sp;
-    I.ev = sp ? -k.eta4 * V : 0.0f;
     return I;
 }
 
-// The same pair terms as pair_force from the staged neighbour (A, B, C as in the staging),
-// without branches on the species: the unlike terms are selected, the viscous-viscous one
-// vanishes through ev and V_j taken only for a viscous neighbour (B.w = -V_j).  KT fixes
-// the smoothing kernel at compile time (-1: the one in k).
-template <int KT = -1>
-__device__ __forceinline__ void pair_force_f32(const ForceK<float> &k, const ForceI32 &I, float im2_0,
-                                               float im2_1, float4 A, float4 B, float4 C, float r0,
-                                               float r1, float r2, float v0, float v1, float v2,
-                                               float hs0, float hs1, float hs2, float f[3], float n[3])
+// Force f on target i from staged neighbour j (A, B, C) and the torque term n' that both
+// receive, the pair terms of Sec. 2.1:
+//   pressure     m_i m_j (P_i/rho_i^2 + P_j/rho_j^2) F r
+//   interfacial  g_T (r_x, r_y, 0), g_T = -sigma_T m_i m_j (1/rho_i^2 + 1/rho_j^2) F, unlike
+//   viscous      -4 eta V_i V_j F (v - hs x r), viscous-viscous pairs
+//   friction     -C_l W (V_i/S_i + V_j/S_j) v, unlike pairs
+//   torque       -1/2 r x (non-central force), returned as n' with torque = -(h/2) n'
+// r = r_s (units of h) = x_i - x_j, v = v_s = v_i - v_j, hs = (w_i + w_j)/2.  No branch on
+// the species: the unlike terms are selected, the viscous-viscous one vanishes through
+// I.ev and V_j taken only for a viscous neighbour (B.w = -V_j).  EQM: equal species masses.
+template <int KT, bool EQM>
+__device__ __forceinline__ void pair_force_f32(const PairK &k, const PairI &I, float4 A, float4 B,
+                                               float4 C, float r0, float r1, float r2, float v0,
+                                               float v1, float v2, float hs0, float hs1, float hs2,
+                                               float f[3], float n[3])
 {
-    float W, Fk;
-    kernel_WF_fast(KT < 0 ? k.kernel : KT, r0 * r0 + r1 * r1 + r2 * r2, k.inv_h, k.wnorm, W, Fk);
+    float W, Fh;
+    shape_WF<KT>(r0 * r0 + r1 * r1 + r2 * r2, W, Fh);
     const bool spj = B.w < 0.0f;
     const bool unl = spj != I.sp;  // a scalar xor of lane masks
-    const float ir2j = B.w * B.w * (spj ? im2_1 : im2_0);
-    const float mFk = I.m * (spj ? k.m1 : k.m0) * Fk;
-    const float gp = mFk * (I.Pr + A.w);
-    const float gT = unl ? -k.sigT * mFk * (I.ir2 + ir2j) : 0.0f;
-    const float gm = unl ? -k.Cl * W * (I.VS + C.w) : 0.0f;
-    const float gv = I.ev * (spj ? -B.w : 0.0f) * Fk;
-    // gm v + gv (v - hs x r), regrouped as (gm + gv) v - gv (hs x r)
-    const float gmv = gm + gv;
-    const float c0 = gmv * v0 - gv * (hs1 * r2 - hs2 * r1);
-    const float c1 = gmv * v1 - gv * (hs2 * r0 - hs0 * r2);
-    const float c2 = gmv * v2 - gv * (hs0 * r1 - hs1 * r0);
+    const float mF = (EQM ? I.kM : I.kM * (spj ? k.mu1 : 1.0f)) * Fh;
+    const float gp = mF * (I.Pr + A.w);
+    const float sT = fmaf(B.w * B.w, EQM ? k.ks0 : (spj ? k.ks1 : k.ks0), I.sT);
+    const float gT = unl ? mF * sT : 0.0f;
+    const float gm = unl ? W * fmaf(C.w, k.kC, I.cVS) : 0.0f;
+    const float gv = I.ev * (spj ? -B.w : 0.0f) * mF;
+    // u = v - hs x r; non-central part c = gm v + gv u
+    const float u0 = fmaf(hs2, r1, fmaf(-hs1, r2, v0));
+    const float u1 = fmaf(hs0, r2, fmaf(-hs2, r0, v1));
+    const float u2 = fmaf(hs1, r0, fmaf(-hs0, r1, v2));
+    const float c0 = fmaf(gm, v0, gv * u0);
+    const float c1 = fmaf(gm, v1, gv * u1);
+    const float c2 = fmaf(gm, v2, gv * u2);
     const float gh = gp + gT;
-    f[0] = gh * r0 + c0;
-    f[1] = gh * r1 + c1;
-    f[2] = gp * r2 + c2;
-    const float hT = 0.5f * gT * r2;
-    n[0] = hT * r1 - 0.5f * (r1 * c2 - r2 * c1);
-    n[1] = -hT * r0 - 0.5f * (r2 * c0 - r0 * c2);
-    n[2] = -0.5f * (r0 * c1 - r1 * c0);
-}
-
-template <bool KAHAN>
-__global__ void __launch_bounds__(kBrickThreads) k_density_brick(DevState s)
-{
-    __shared__ BrickFrame F;
-    __shared__ WindowTable win;
-    __shared__ float4 stage[kStageDensity];
-    const uint32_t brick = blockIdx.x;
-    const uint32_t bxyz = s.brick_xyz[brick];
-    const InstDesc *d = s.desc + s.brick_inst[brick];
-    const uint8_t *SK = s.sk[s.cur];
-    brick_frame(s, d, brick, bxyz, F, kStageDensity);
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int ts[3];
-    const bool has_cell = brick_target(d, bxyz, w, ts);
-    const int tslot = slot_index(ts[0], ts[1], ts[2]);
-    uint32_t err = 0;
-    if (!F.ok) {
-        if (has_cell) {
-            const uint32_t nt = F.off[tslot + 1] - F.off[tslot];
-            for (uint32_t i = lane; i < nt; i += 64)
-                err |= density_one<float, KAHAN>(s, d, F.begin[tslot] + i);
-        }
-        if (err) atomicOr(s.err, err);
-        return;
-    }
-    stage_density(s, F, stage);
-    __syncthreads();
-    if (!has_cell) return;
-    const uint32_t nt = F.off[tslot + 1] - F.off[tslot];
-    const float cut2 = (float)d->cut2, inv_h = (float)d->inv_h, wnorm = (float)d->wnorm;
-    const int kernel = d->kernel;
-    for (uint32_t chunk = 0; chunk < nt; chunk += 64) {
-        const int ntc = (int)min(64u, nt - chunk);
-        const int G = 64 / ntc;
-        const int g = lane / ntc, t = lane % ntc;
-        const bool active = g < G;
-        const uint32_t kself = F.off[tslot] + chunk + t;
-        float4 me = stage[active ? kself : F.off[tslot]];
-        if (!active) me.x = __builtin_inff();  // no candidate is within reach
-        Acc<float, KAHAN> sw, su;
-        auto wval = [&](const float4 &c) {
-            const float d0 = me.x - c.x, d1 = me.y - c.y, d2 = me.z - c.z;
-            const float q = fast_sqrt(d0 * d0 + d1 * d1 + d2 * d2) * inv_h;
-            if (kernel == KERNEL_WENDLAND) {
-                const float tt = 1.0f - 0.5f * q;
-                const float t2 = tt * tt;
-                return wnorm * t2 * t2 * (2.0f * q + 1.0f);
-            }
-            if (q < 1.0f) return wnorm * (1.0f - 1.5f * q * q + 0.75f * q * q * q);
-            const float tt = 2.0f - q;
-            return wnorm * 0.25f * tt * tt * tt;
-        };
-        const bool rec_ok = masks_fit(F, ts, G);
-        uint64_t *rec = (rec_ok && active)
-                            ? s.masks + (size_t)(F.begin[tslot] + chunk + t) * kMaskSlots + g
-                            : nullptr;
-        stencil_windows(F, win[w], ts, lane, active ? g : 0, G, rec_ok, false, rec,
-            [&](uint32_t k, bool in_row) {
-                const float4 c = stage[k];
-                const float d0 = me.x - c.x, d1 = me.y - c.y, d2 = me.z - c.z;
-                return in_row & (k != kself) & (d0 * d0 + d1 * d1 + d2 * d2 < cut2);
-            },
-            [&](uint32_t k) {
-                const float4 c = stage[k];
-                const float W = wval(c);
-                sw.add(W);
-                su.add(c.w != me.w ? W : 0.0f);
-            });
-        const double SW = group_total(sw.s, KAHAN ? sw.c : 0.0f, lane, ntc, G);
-        const double SU = group_total(su.s, KAHAN ? su.c : 0.0f, lane, ntc, G);
-        if (active && g == 0) {
-            const uint32_t p = F.begin[tslot] + chunk + t;
-            const uint8_t ski = SK[p];
-            err |= density_finish<float>(s, d, p, ski & 1, ski >> 1, SW, SU);
-        }
-    }
-    if (err) atomicOr(s.err, err);
-}
-
-template <bool KAHAN>
-__global__ void __launch_bounds__(kBrickThreads) k_force_brick(DevState s)
-{
-    __shared__ BrickFrame F;
-    __shared__ WindowTable win;
-    __shared__ float4 SA[kStageForce];   // position (brick frame), P/rho^2
-    __shared__ float4 SB[kStageForce];   // velocity - v_ref, V (negative: viscous species)
-    __shared__ float4 SC[kStageForce];   // half the spin, V/S
-    __shared__ double vref[3];
-    const uint32_t brick = blockIdx.x;
-    const uint32_t bxyz = s.brick_xyz[brick];
-    const InstDesc *d = s.desc + s.brick_inst[brick];
-    const uint8_t *SK = s.sk[s.cur];
-    const uint32_t M = brick_frame(s, d, brick, bxyz, F, kStageForce, s.v[s.cur], vref);
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int ts[3];
-    const bool has_cell = brick_target(d, bxyz, w, ts);
-    const int tslot = slot_index(ts[0], ts[1], ts[2]);
-    uint32_t err = 0;
-    if (!F.ok) {
-        if (has_cell) {
-            const uint32_t nt = F.off[tslot + 1] - F.off[tslot];
-            for (uint32_t i = lane; i < nt; i += 64) err |= force_one<float, KAHAN>(s, d, F.begin[tslot] + i);
-        }
-        if (err) atomicOr(s.err, err);
-        return;
-    }
-    stage_force(s, F, M, vref, SA, SB, SC);
-    __syncthreads();
-    if (!has_cell) return;
-    const uint32_t nt = F.off[tslot + 1] - F.off[tslot];
-    const float cut2 = (float)d->cut2;
-    const ForceK<float> K(d);
-    const float im2_0 = (float)(1.0 / (d->mass[0] * d->mass[0]));
-    const float im2_1 = (float)(1.0 / (d->mass[1] * d->mass[1]));
-    for (uint32_t chunk = 0; chunk < nt; chunk += 64) {
-        const int ntc = (int)min(64u, nt - chunk);
-        const int G = 64 / ntc;
-        const int g = lane / ntc, t = lane % ntc;
-        const bool target = g < G;
-        const uint32_t kself = F.off[tslot] + chunk + t;
-        const uint32_t p = F.begin[tslot] + chunk + t;
-        const bool fluid = target && (SK[p] >> 1) == KIND_FLUID;
-        const uint32_t ki = target ? kself : F.off[tslot];
-        const float4 Ai = SA[ki], Bi = SB[ki], Ci = SC[ki];
-        const ForceI32 I = force_target(K, Ai, Bi, Ci, im2_0, im2_1);
-        const int spi = Bi.w < 0.0f ? 1 : 0;
-        Acc<float, KAHAN> F0, F1, F2, T0, T1, T2;
-        auto pair = [&](const float4 &A, const float4 &B, const float4 &C, float f[3], float n[3]) {
-            pair_force_f32(K, I, im2_0, im2_1, A, B, C, Ai.x - A.x, Ai.y - A.y, Ai.z - A.z,
-                           Bi.x - B.x, Bi.y - B.y, Bi.z - B.z, Ci.x + C.x, Ci.y + C.y, Ci.z + C.z, f, n);
-        };
-        auto accum = [&](const float f[3], const float n[3]) {
-            F0.add(f[0]); F1.add(f[1]); F2.add(f[2]);
-            T0.add(n[0]); T1.add(n[1]); T2.add(n[2]);
-        };
-        const bool replay = masks_fit(F, ts, G);
-        const uint64_t *recp = (replay && fluid) ? s.masks + (size_t)p * kMaskSlots + g : nullptr;
-        stencil_windows(F, win[w], ts, lane, target ? g : 0, G, false, replay,
-                        const_cast<uint64_t *>(recp),
-            [&](uint32_t k, bool in_row) {
-                const float4 c = SA[k];
-                const float d0 = Ai.x - c.x, d1 = Ai.y - c.y, d2 = Ai.z - c.z;
-                return in_row & fluid & (k != kself) & (d0 * d0 + d1 * d1 + d2 * d2 < cut2);
-            },
-            [&](uint32_t k) {
-                float f[3], n[3];
-                pair(SA[k], SB[k], SC[k], f, n);
-                accum(f, n);
-            });
-        const double f0 = group_total(F0.s, KAHAN ? F0.c : 0.0f, lane, ntc, G);
-        const double f1 = group_total(F1.s, KAHAN ? F1.c : 0.0f, lane, ntc, G);
-        const double f2 = group_total(F2.s, KAHAN ? F2.c : 0.0f, lane, ntc, G);
-        const double t0 = group_total(T0.s, KAHAN ? T0.c : 0.0f, lane, ntc, G);
-        const double t1 = group_total(T1.s, KAHAN ? T1.c : 0.0f, lane, ntc, G);
-        const double t2 = group_total(T2.s, KAHAN ? T2.c : 0.0f, lane, ntc, G);
-        if (target && g == 0) {
-            const double FF[3] = {fluid ? f0 : 0.0, fluid ? f1 : 0.0, fluid ? f2 : 0.0};
-            const double TT[3] = {fluid ? t0 : 0.0, fluid ? t1 : 0.0, fluid ? t2 : 0.0};
-            err |= force_finish<float>(s, d, p, spi, FF, TT);
-        }
-    }
-    if (err) atomicOr(s.err, err);
+    f[0] = fmaf(gh, r0, c0);
+    f[1] = fmaf(gh, r1, c1);
+    f[2] = fmaf(gp, r2, c2);
+    // n' = r x c - gT r_z (r_y, -r_x, 0)
+    const float dz = fmaf(-gT, r2, c2);
+    n[0] = fmaf(r1, dz, -r2 * c1);
+    n[1] = fmaf(r2, c0, -r0 * dz);
+    n[2] = fmaf(r0, c1, -r1 * c0);
 }
 
 // ------------------------------------------------------ candidate-major brick sweeps ---
-// Same bricks, staging and fallbacks as above, with the neighbour test turned around.  The
-// wave of a target cell lays the candidates of its 27-cell stencil (nine rows of three
+// The wave of a target cell lays the candidates of its 27-cell stencil (nine rows of three
 // x-adjacent cells, each a contiguous run of the staged particles) out as one list, held
 // in registers as windows of 64 candidates, one per lane.  Testing one target against a
 // window is then one 64-lane comparison whose ballot is the window's hit mask, so targets
@@ -1266,7 +1071,7 @@ __device__ __forceinline__ StencilList stencil_list(const BrickFrame &F, const i
     }
     S.C = acc;
     S.NW = (acc + 63) / 64;
-    __builtin_amdgcn_wave_barrier();
+    wave_lds_handoff();
     return S;
 }
 
@@ -1311,27 +1116,15 @@ __device__ __forceinline__ void hit_share(Word &&word, uint32_t H, int g, int G,
     mc = drop_low_bits(mc, skip);
 }
 
-__device__ __forceinline__ float kernel_W_fast(int kernel, float r2, float inv_h, float wnorm)
-{
-    const float q = fast_sqrt(r2) * inv_h;
-    if (kernel == KERNEL_WENDLAND) {
-        const float t = 1.0f - 0.5f * q;
-        const float t2 = t * t;
-        return wnorm * t2 * t2 * (2.0f * q + 1.0f);
-    }
-    if (q < 1.0f) return wnorm * (1.0f - 1.5f * q * q + 0.75f * q * q * q);
-    const float t = 2.0f - q;
-    return wnorm * 0.25f * t * t * t;
-}
 
 // Ballot tests of targets kbase .. kbase + ntc - 1 (staged indices) against the first NWc
 // candidate windows, NWc fixed at compile time so that the windows need no branch per
 // target.  Lane t ORs target t's masks into mlo/mhi (low and high halves).
 // The test is |c - t|^2 < cut2 expanded as |c|^2 - 2 c.t < cut2 - |t|^2, with the
 // candidate's -2c (px, py, pz) and |c|^2 (cc) precomputed: three FMAs and a compare per
-// target and window.  Positions are relative to the brick centre (|c|^2 <= 48 h^2), so the
-// expanded form can misjudge only pairs within a few 1e-6 of the support radius, where W
-// and F are below 1e-17 of their scale.
+// target and window.  Positions are relative to the brick centre in units of h
+// (|c|^2 <= 48), so the expanded form can misjudge only pairs within a few 1e-6 of the
+// support radius, where W and F are below 1e-17 of their scale.
 template <int NWc>
 __device__ __forceinline__ void test_targets(const float4 *stage, const float *px, const float *py,
                                              const float *pz, const float *cc, uint32_t kbase,
@@ -1380,7 +1173,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
         if (err) atomicOr(s.err, err);
         return;
     }
-    stage_density(s, F, stage);
+    stage_density(s, F, d->inv_h, stage);
     __syncthreads();
     if (!has_cell) return;
     const uint32_t toff = __builtin_amdgcn_readfirstlane(F.off[tslot]);
@@ -1406,7 +1199,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
             cc[c] = q.x * q.x + q.y * q.y + q.z * q.z;
         }
     }
-    const float cut2 = (float)d->cut2, inv_h = (float)d->inv_h, wnorm = (float)d->wnorm;
+    const float cut2 = (float)(d->cut2 * d->inv_h * d->inv_h);  // positions in units of h
     const int kernel = d->kernel;
     // compiled once per smoothing kernel, chosen per brick (as in the force sweep)
     auto sweep = [&](auto kt) {
@@ -1454,7 +1247,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
                     }
                 }
             }
-            __builtin_amdgcn_wave_barrier();
+            wave_lds_handoff();
             // kernel sums: lanes (target tt, group g)
             const int G = 64 / (int)ntc;
             const int g = lane / (int)ntc, tt = lane % (int)ntc;
@@ -1480,18 +1273,18 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
             for (uint32_t i = 0; i < cnt; i++) {
                 const float4 qc = next_hit();
                 const float d0 = me.x - qc.x, d1 = me.y - qc.y, d2 = me.z - qc.z;
-                const float W = kernel_W_fast(KT, d0 * d0 + d1 * d1 + d2 * d2, inv_h, wnorm);
+                const float W = shape_W<KT>(d0 * d0 + d1 * d1 + d2 * d2);
                 sw.add(W);
                 su.add(qc.w != me.w ? W : 0.0f);
             }
-            const double SW = group_total(sw.s, KAHAN ? sw.c : 0.0f, lane, (int)ntc, G);
-            const double SU = group_total(su.s, KAHAN ? su.c : 0.0f, lane, (int)ntc, G);
+            const double SW = d->wnorm * group_total(sw.s, KAHAN ? sw.c : 0.0f, lane, (int)ntc, G);
+            const double SU = d->wnorm * group_total(su.s, KAHAN ? su.c : 0.0f, lane, (int)ntc, G);
             if (act && g == 0) {
                 const uint32_t p = pbase + t0 + tt;
                 const uint8_t ski = SK[p];
                 err |= density_finish<float>(s, d, p, ski & 1, ski >> 1, SW, SU);
             }
-            __builtin_amdgcn_wave_barrier();  // the masks are rewritten by the next round
+            wave_lds_handoff();  // the masks are rewritten by the next round
         }
     };
     if (kernel == KERNEL_WENDLAND) sweep(std::integral_constant<int, KERNEL_WENDLAND>());
@@ -1526,7 +1319,7 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
         if (err) atomicOr(s.err, err);
         return;
     }
-    stage_force(s, F, M, vref, SA, SB, SC);
+    stage_force(s, F, M, vref, d->inv_h, SA, SB, SC);
     __syncthreads();
     if (!has_cell) return;
     const uint32_t toff = F.off[tslot], pbase = F.begin[tslot];
@@ -1538,16 +1331,16 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
         if (err) atomicOr(s.err, err);
         return;
     }
-    const ForceK<float> K(d);
-    const float im2_0 = (float)(1.0 / (d->mass[0] * d->mass[0]));
-    const float im2_1 = (float)(1.0 / (d->mass[1] * d->mass[1]));
+    const PairK K(d);
+    const double th = -0.5 * d->h;  // torque = -(h/2) n'
     const int NW = (int)S.NW;
     // Per block of up to 64 targets: wall targets get zero force and torque directly, and the
     // fluid targets share the lanes as (target, group g of G), so walls take no lanes.
-    // Compiled once per smoothing kernel, chosen per brick (a batch may mix kernels), so
-    // that the hit loop carries no branch on it.
-    auto sweep = [&](auto kt) {
+    // Compiled once per smoothing kernel and for equal or unequal species masses, chosen
+    // per brick (a batch may mix them), so that the hit loop carries no branch on them.
+    auto sweep = [&](auto kt, auto eqm) {
         constexpr int KT = decltype(kt)::value;
+        constexpr bool EQM = decltype(eqm)::value;
         for (uint32_t t0 = 0; t0 < nt; t0 += 64) {
             const uint32_t nb = min(64u, nt - t0);
             uint32_t sk_t = 0;
@@ -1567,7 +1360,7 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
             const uint32_t p = pbase + t0 + t;
             const uint32_t ki = toff + t0 + t;
             const float4 Ai = SA[ki], Bi = SB[ki], Ci = SC[ki];
-            const ForceI32 I = force_target(K, Ai, Bi, Ci, im2_0, im2_1);
+            const PairI I = pair_target(K, Ai, Bi, Ci);
             // all of the target's mask words at once (no chain of dependent loads); group g
             // takes hits [lo, lo + cnt) in list order, starting in window c
             const uint64_t *gm = s.masks + (size_t)p * kMaskSlots;
@@ -1614,9 +1407,9 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
                 const uint32_t k = next_k();
                 const float4 A = SA[k], B = SB[k], C = SC[k];
                 float f[3], nn[3];
-                pair_force_f32<KT>(K, I, im2_0, im2_1, A, B, C, Ai.x - A.x, Ai.y - A.y, Ai.z - A.z,
-                                   Bi.x - B.x, Bi.y - B.y, Bi.z - B.z, Ci.x + C.x, Ci.y + C.y,
-                                   Ci.z + C.z, f, nn);
+                pair_force_f32<KT, EQM>(K, I, A, B, C, Ai.x - A.x, Ai.y - A.y, Ai.z - A.z,
+                                        Bi.x - B.x, Bi.y - B.y, Bi.z - B.z, Ci.x + C.x, Ci.y + C.y,
+                                        Ci.z + C.z, f, nn);
                 F0.add(f[0]); F1.add(f[1]); F2.add(f[2]);
                 T0.add(nn[0]); T1.add(nn[1]); T2.add(nn[2]);
             }
@@ -1628,13 +1421,23 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
             const double q2 = group_total(T2.s, KAHAN ? T2.c : 0.0f, lane, n, G);
             if (target && g == 0) {
                 const double FF[3] = {f0, f1, f2};
-                const double TT[3] = {q0, q1, q2};
+                const double TT[3] = {th * q0, th * q1, th * q2};
                 err |= force_finish<float>(s, d, p, I.sp ? 1 : 0, FF, TT);
             }
         }
     };
-    if (d->kernel == KERNEL_WENDLAND) sweep(std::integral_constant<int, KERNEL_WENDLAND>());
-    else sweep(std::integral_constant<int, KERNEL_CUBIC>());
+    using Wend = std::integral_constant<int, KERNEL_WENDLAND>;
+    using Cub = std::integral_constant<int, KERNEL_CUBIC>;
+    using Eq = std::integral_constant<bool, true>;
+    using Uneq = std::integral_constant<bool, false>;
+    const bool eq = d->mass[0] == d->mass[1];
+    if (d->kernel == KERNEL_WENDLAND) {
+        if (eq) sweep(Wend(), Eq());
+        else sweep(Wend(), Uneq());
+    } else {
+        if (eq) sweep(Cub(), Eq());
+        else sweep(Cub(), Uneq());
+    }
     if (err) atomicOr(s.err, err);
 }
 
@@ -1879,10 +1682,9 @@ hipError_t launch_density(const DevState &d, const Launch &L, hipStream_t st)
 {
     unsigned g = grid_for(d.n_waves, L.bs_density);
     if (d.precision == 0) k_density<double, false><<<g, L.bs_density, 0, st>>>(d);
-    else if ((L.sweep == SWEEP_BRICK || L.sweep == SWEEP_CAND) && d.n_bricks) {
+    else if (L.sweep == SWEEP_CAND && d.n_bricks) {
         k_brick_frames<<<d.n_bricks, 64, 0, st>>>(d);
-        if (L.sweep == SWEEP_BRICK) k_density_brick<true><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
-        else k_density_cand<true><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
+        k_density_cand<true><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
     }
     else k_density<float, true><<<g, L.bs_density, 0, st>>>(d);
     return hipGetLastError();
@@ -1892,7 +1694,6 @@ hipError_t launch_force(const DevState &d, const Launch &L, hipStream_t st)
 {
     unsigned g = grid_for(d.n_waves, L.bs_force);
     if (d.precision == 0) k_force<double, false><<<g, L.bs_force, 0, st>>>(d);
-    else if (L.sweep == SWEEP_BRICK && d.n_bricks) k_force_brick<true><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
     else if (L.sweep == SWEEP_CAND && d.n_bricks) k_force_cand<true><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
     else k_force<float, true><<<g, L.bs_force, 0, st>>>(d);
     return hipGetLastError();

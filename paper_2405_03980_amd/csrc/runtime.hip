@@ -695,7 +695,10 @@ sph_status sph_batch_set_tuning(sph_batch *b, const sph_tuning *t)
             return SPH_E_INVALID;
         }
     if (t->use_graph < -1 || t->use_graph > 1) { b->err = "use_graph must be -1, 0 or 1"; return SPH_E_INVALID; }
-    if (t->sweep < 0 || t->sweep > 3) { b->err = "sweep must be 0, 1, 2 or 3"; return SPH_E_INVALID; }
+    if (t->sweep != 0 && t->sweep != 1 && t->sweep != 3) {
+        b->err = "sweep must be 0 (keep), 1 (per particle) or 3 (brick, candidate ballots)";
+        return SPH_E_INVALID;
+    }
     if (t->sweep) b->L.sweep = t->sweep;
     if (t->block_density) b->L.bs_density = t->block_density;
     if (t->block_force) b->L.bs_force = t->block_force;

@@ -78,8 +78,9 @@ struct DevState {
 constexpr int kMaskSlots = 16;
 
 // Sweep implementations: one thread per particle walking its own cell stencil, or one
-// workgroup per 2x2x2-cell brick with the brick's neighbourhood staged in LDS.
-enum { SWEEP_THREAD = 1, SWEEP_BRICK = 2, SWEEP_CAND = 3 };
+// workgroup per 2x2x2-cell brick with the brick's neighbourhood staged in LDS and the
+// neighbour test done by wave ballots over candidates.  (Value 2 is not used.)
+enum { SWEEP_THREAD = 1, SWEEP_CAND = 3 };
 
 struct Launch {
     int bs_density = 256, bs_force = 256, bs_stream = 256;

@@ -22,13 +22,12 @@ from . import inputs as I
 
 
 def candidates(batch: bool):
-    """Settings to try: both kinds of brick sweeps (cell factor 1) with a few streaming block
-    sizes, and per-particle sweeps for cell factors 1 and 2 over block sizes."""
+    """Settings to try: the brick sweeps (cell factor 1) with a few streaming block sizes,
+    and per-particle sweeps for cell factors 1 and 2 over block sizes."""
     out = []
-    for sweep in (3, 2):
-        for bs in (128, 256, 512):
-            for graph in ((1,) if batch else (0, 1)):
-                out.append(dict(cell_factor=1, sweep=sweep, block_stream=bs, use_graph=graph))
+    for bs in (128, 256, 512):
+        for graph in ((1,) if batch else (0, 1)):
+            out.append(dict(cell_factor=1, sweep=3, block_stream=bs, use_graph=graph))
     for cf, bd, bf in itertools.product((1, 2), (128, 256), (64, 128, 256)):
         out.append(dict(cell_factor=cf, sweep=1, block_density=bd, block_force=bf,
                         block_stream=256, use_graph=1))

@@ -34,9 +34,9 @@ def _sim(w, prec, name):
     from paper_2405_03980_amd import sim as S
     tun, cf = _tuned(name)
     s = S.Simulation(dict(w.params, cell_factor=cf), w.n, precision=prec)
-    s.init(w.x, w.v, w.omega, w.species, w.kind)
     if tun:
-        s.set_tuning(**tun)
+        s.set_tuning(**tun)  # before init, so that the first evaluation uses it too
+    s.init(w.x, w.v, w.omega, w.species, w.kind)
     return s
 
 

@@ -19,10 +19,12 @@ FP64, MIXED = L.FP64, L.FP32_MIXED
 
 
 def _sim(w, prec, **tune):
+    """A simulation of w whose first evaluation (at init) already uses the given tuning."""
     from paper_2405_03980_amd import sim as S
-    s = S.simulation_from(w, precision=prec)
+    s = S.Simulation(w.params, w.n, precision=prec)
     if tune:
         s.set_tuning(**tune)
+    s.init(w.x, w.v, w.omega, w.species, w.kind)
     return s
 
 
@@ -204,8 +206,32 @@ def test_batch_mixing_kernels_and_geometries():
             assert e[k] < 1e-5, (i, k, e[k])
 
 
-@pytest.mark.parametrize("sweep", [2, 3])
-def test_three_cell_periodic_box(sweep):
+@pytest.mark.parametrize("prec,sweep,tol", [(FP64, None, 1e-12), (MIXED, 1, 1e-5), (MIXED, 3, 1e-5)])
+def test_unequal_species_masses(prec, sweep, tol):
+    """Per-species masses (the viscous species 5% heavier, so its lattice density sits 5%
+    above rho0): every sweep takes its unequal-mass form of the mass-dependent pair factors,
+    from the first evaluation on."""
+    w = _jitter_box(12, seed=11)
+    m = float(O.default_mass(w.params)[0])
+    w.params = dict(w.params, mass=[m, 1.05 * m])
+    print(f"[masses] prec={prec} sweep={sweep} n={w.n}", flush=True)
+    ref = O.State.from_workload(w)
+    s = _sim(w, prec, sweep=sweep) if sweep else _sim(w, prec)
+    e = field_errors(s.read(), ref, w)
+    print("unequal masses, first evaluation", e, flush=True)
+    for k in ("rho", "P", "acc", "alpha"):
+        assert e[k] < tol, (k, e[k])
+    ref.step(1e-4, w.Omega, 3)
+    s.step(1e-4, w.Omega, 3)
+    e = field_errors(s.read(), ref, w)
+    print("unequal masses, 3 steps", e, flush=True)
+    assert positions_ok(e, tol, 3), e
+    for k in ("v", "omega", "rho", "P"):
+        assert e[k] < tol, (k, e[k])
+    s.close()
+
+
+def test_three_cell_periodic_box():
     """A periodic box only three cells wide: each brick's 4x4x4 neighbourhood wraps onto
     itself (one cell staged twice, under two image shifts) and must still give each target
     every neighbour exactly once."""
@@ -214,14 +240,14 @@ def test_three_cell_periodic_box(sweep):
     dims, _ = O_.grid_dims(w.params)
     assert list(dims) == [3, 3, 3], dims
     ref = O.State.from_workload(w)
-    s = _sim(w, MIXED, sweep=sweep)
+    s = _sim(w, MIXED, sweep=3)
     e = field_errors(s.read(), ref, w)
     for k in ("rho", "P", "acc", "alpha"):
         assert e[k] < 1e-5, (k, e[k])
     ref.step(1e-4, w.Omega, 2)
     s.step(1e-4, w.Omega, 2)
     e = field_errors(s.read(), ref, w)
-    print("3-cell box", sweep, e, flush=True)
+    print("3-cell box", e, flush=True)
     assert positions_ok(e, 1e-5, 2), e
     for k in ("v", "omega", "rho", "P"):
         assert e[k] < 1e-5, (k, e[k])
@@ -348,11 +374,11 @@ def test_step_before_init_is_a_state_error():
     s.close()
 
 
-@pytest.mark.parametrize("sweep", [2, 3])
 @pytest.mark.parametrize("case", ["cylinder", "box4096", "jitter"])
-def test_brick_sweep_matches_thread_sweep(case, sweep):
-    """The LDS-staged brick sweeps (target-major and candidate-major) and the per-particle
-    sweeps compute the same FP32-mixed fields up to single-precision rounding."""
+def test_brick_sweep_matches_thread_sweep(case):
+    """The LDS-staged brick sweeps and the per-particle sweeps compute the same FP32-mixed
+    fields up to single-precision rounding."""
+    sweep = 3
     w = CELL_CASES[case]()
     print(f"[brick] {case} sweep={sweep} n={w.n}", flush=True)
     a = _sim(w, MIXED, sweep=sweep)
@@ -370,10 +396,10 @@ def test_brick_sweep_matches_thread_sweep(case, sweep):
     b.close()
 
 
-@pytest.mark.parametrize("sweep", [2, 3])
 @pytest.mark.parametrize("h_factor", [1.6, 2.2])
-def test_brick_fallback_when_cells_are_full(h_factor, sweep):
+def test_brick_fallback_when_cells_are_full(h_factor):
     """Neighbourhoods too large to stage fall back to the per-particle code path."""
+    sweep = 3
     w = I.make_box(20, kernel=I.KERNEL_WENDLAND_C2, h_factor=h_factor)
     print(f"[fallback] h/dx={h_factor} sweep={sweep} n={w.n}", flush=True)
     ref = O.State.from_workload(w)
@@ -382,6 +408,18 @@ def test_brick_fallback_when_cells_are_full(h_factor, sweep):
     print("fallback", h_factor, e, flush=True)
     for k in ("rho", "P", "acc", "alpha"):
         assert e[k] < 1e-5, (k, e[k])
+    s.close()
+
+
+@pytest.mark.parametrize("value", [2, 4, -1])
+def test_tuning_rejects_unknown_sweep(value):
+    """Only 0 (keep), 1 and 3 name a sweep; anything else is an argument error that leaves
+    the current setting alone."""
+    s = _sim(I.make_box(8), MIXED)
+    with pytest.raises(L.SphError) as e:
+        s.set_tuning(sweep=value)
+    assert e.value.status == L.E_INVALID
+    assert s.get_tuning()["sweep"] == 3
     s.close()
 
 
