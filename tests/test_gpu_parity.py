@@ -411,6 +411,29 @@ def test_brick_fallback_when_cells_are_full(h_factor):
     s.close()
 
 
+@pytest.mark.parametrize("prec,sweep", [(FP64, None), (MIXED, 1), (MIXED, 3)])
+def test_overfull_cell_is_a_capacity_error(prec, sweep):
+    """1,100 particles gathered in one cell (more than the 1,024 the search walks): the
+    sweeps skip that cell, every kernel stays bounded, and the next synchronising call
+    reports SPH_E_CAPACITY."""
+    w = I.make_box(12, kernel=I.KERNEL_WENDLAND_C2)
+    rng = np.random.default_rng(5)
+    lo, edge = 0.25, 0.25  # cell (1, 1, 1) of the 4x4x4 grid
+    w.x = w.x.copy()
+    w.x[:, :1100] = lo + edge * rng.uniform(0.05, 0.95, size=(3, 1100))
+    w.v = np.zeros_like(w.v)
+    print(f"[capacity] prec={prec} sweep={sweep} n={w.n}", flush=True)
+    from paper_2405_03980_amd import sim as S
+    s = S.Simulation(w.params, w.n, precision=prec)
+    if sweep:
+        s.set_tuning(sweep=sweep)
+    with pytest.raises(L.SphError) as e:
+        s.init(w.x, w.v, w.omega, w.species, w.kind)
+        s.sync()
+    assert e.value.status == L.E_CAPACITY, e.value
+    s.close()
+
+
 @pytest.mark.parametrize("value", [2, 4, -1])
 def test_tuning_rejects_unknown_sweep(value):
     """Only 0 (keep), 1 and 3 name a sweep; anything else is an argument error that leaves
