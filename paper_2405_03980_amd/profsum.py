@@ -45,8 +45,7 @@ COMMANDS = [
 VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
 COPY_MIB = 1024
 KERNEL_GROUPS = {"k_keys<float>": "keys", "k_scatter": "scatter", "k_reorder<float>": "reorder",
-                 "k_density_cand<true>": "density", "k_force_cand<true>": "force",
-                 "k_density_brick<true>": "density", "k_force_brick<true>": "force"}
+                 "k_density_cand<true>": "density", "k_force_cand<true>": "force"}
 
 
 def source_sha() -> str:
