@@ -161,6 +161,27 @@ sph_status sph_read_fields(sph_sim *s, double *x, double *v, double *omega, doub
  * out[0..2] = sum m v, out[3..5] = sum (m x × v + I omega), out[6] = kinetic + spin energy. */
 sph_status sph_diagnostics(sph_sim *s, double out[7]);
 
+/* Vortex diagnostic (the image analysis of Sec. 3: vortices are counted on the z = 0
+ * section of the rotational-force intensity, the fifth term of Eq. 2).
+ * sph_vortex_dims: pixels per row (nx) and rows (ny) of the image, squares of side dx over
+ * [lo, hi) in x and y, n = ceil((hi - lo) / dx - 1e-9).  Host only.
+ * sph_vortex_image: for the fluid particles with -dx <= z - z0 < dx (z taken periodic),
+ * the intensity I = |sum over viscous neighbours j (walls included) of
+ * 2 eta V_j F_ij (w_i + w_j) x r_ij| (FP64, from the current state and density), which is
+ * the spin part of the viscous pair force per unit volume; image[iy][ix] = the largest I
+ * in the pixel (0 if none).  Pixels with a positive value of at least theta times the
+ * largest are on; labels[iy][ix] = the smallest pixel index iy nx + ix of the pixel's
+ * 8-connected component of on pixels, -1 when off; *count (host) = the number of
+ * components with at least min_pixels pixels.  image (double, nx ny), labels (int32,
+ * nx ny) and scratch (int32, nx ny + 8, 8-byte aligned) are caller-owned device buffers
+ * on the simulation's stream; the call synchronises.  SPH_E_INVALID for a missing
+ * buffer, an unaligned scratch, non-finite z0 or theta, theta < 0 or min_pixels < 1;
+ * SPH_E_STATE before init.  The labels and the count do not depend on the order of any
+ * floating-point sum other than the intensities'. */
+sph_status sph_vortex_dims(const sph_params *p, int32_t *nx, int32_t *ny);
+sph_status sph_vortex_image(sph_sim *s, double z0, double theta, int32_t min_pixels,
+                            double *image, int32_t *labels, int32_t *scratch, int32_t *count);
+
 /* Cell list of the last neighbour search (device outputs).  key_by_id[n]: Morton code of
  * the particle's cell (bit 0 = x); perm[n]: particle ids sorted by (key, id);
  * cell_start[ncell + 1]: CSR offsets of the cells taken in Morton order, ncell being the

@@ -78,7 +78,8 @@ def lib():
         L.or_neighbors.restype = C.c_int64
         L.or_num_threads.restype = C.c_int
         for name in ("or_cells", "or_density", "or_forces", "or_evaluate", "or_step",
-                     "or_diagnostics", "or_default_mass", "or_grid_dims", "or_eval_subset"):
+                     "or_diagnostics", "or_default_mass", "or_grid_dims", "or_eval_subset",
+                     "or_rot_intensity"):
             getattr(L, name).restype = C.c_int
         _ = (dp, pp)
         _lib = L
@@ -244,6 +245,22 @@ def eval_subset(params, x, v, omega, species, kind, idx):
                                 _p(_c(kind, np.uint8)), C.c_int64(k), _p(idx), _p(rho), _p(P),
                                 _p(S), _p(acc), _p(alpha)))
     return rho, P, S, acc, alpha
+
+
+def rot_intensity(params, x, omega, species, kind, rho, mask=None):
+    """Rotational-force intensity |2 eta sum_j V_j F_ij (w_i + w_j) x r_ij| over the viscous
+    neighbours of every fluid particle (Eq. 2, fifth term; 0 for other particles).  With a
+    boolean mask only those particles are evaluated (rho is read for their neighbours)."""
+    x = _c(x, np.float64)
+    n = x.shape[1]
+    out = np.zeros(n)
+    p = params_from(params)
+    m = _c(mask, np.uint8) if mask is not None else None
+    _check(lib().or_rot_intensity(C.byref(p), C.c_int64(n), _p(x), _p(_c(omega, np.float64)),
+                                  _p(_c(species, np.uint8)), _p(_c(kind, np.uint8)),
+                                  _p(_c(rho, np.float64)), _p(m) if m is not None else None,
+                                  _p(out)))
+    return out
 
 
 def num_threads() -> int:

@@ -728,6 +728,60 @@ int or_diagnostics(const or_params *p, int64_t n, const double *x, const double 
     return OR_OK;
 }
 
+/* ------------------------------------------------------------------------------------
+ * Rotational-force intensity (the diagnostic the paper renders and counts vortices on,
+ * Sec. 3 with Figs. of the z = 0 section): the fifth term of Eq. 2, 2 eta_r curl(omega_0),
+ * in the model's own discretisation.  The spin part of the viscous pair force is
+ * 2 eta V_i V_j F_ij (w_i + w_j) x r_ij (viscous pairs), so per unit volume of particle i
+ *     s_i = sum over viscous neighbours j of 2 eta V_j F_ij (w_i + w_j) x r_ij,
+ * and the intensity is |s_i|.  It is evaluated at every fluid particle (the paper colours
+ * both components by it), always from the viscous neighbours (walls included, as in the
+ * pair forces); other particles get 0.  rho is the density of the same state; with a
+ * mask (NULL: all particles) only the masked particles are evaluated, and rho is read only
+ * for their viscous neighbours.
+ * ---------------------------------------------------------------------------------- */
+int or_rot_intensity(const or_params *p, int64_t n, const double *x, const double *w,
+                     const uint8_t *species, const uint8_t *kind, const double *rho,
+                     const uint8_t *mask, double *out)
+{
+    cells_t c;
+    int st = cells_build(p, n, x, &c);
+    if (st) return st;
+    double m[2];
+    particle_masses(p, m);
+    int err = 0;
+#pragma omp parallel
+    {
+        nbuf_t b = {0, 0};
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t i = 0; i < n; i++) {
+            out[i] = 0.0;
+            if (kind[i] != OR_FLUID || (mask && !mask[i])) continue;
+            double s[3] = {0, 0, 0};
+            int64_t cnt = neighbours(p, &c, n, x, i, 0, &b);
+            for (int64_t k = 0; k < cnt; k++) {
+                int64_t j = b.ids[k];
+                if (species[j] != 1) continue;
+                double r[3];
+                within(p, &c.g, n, x, i, j, r);
+                double rr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+                double Fij = kernel_F(p->kernel, p->h, rr);
+                double Vj = m[species[j]] / rho[j];
+                double ws[3], t[3];
+                for (int a = 0; a < 3; a++) ws[a] = w[a * n + i] + w[a * n + j];
+                cross(ws, r, t);
+                double g = 2.0 * p->eta * Vj * Fij;
+                for (int a = 0; a < 3; a++) s[a] += g * t[a];
+            }
+            out[i] = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+            if (!isfinite(out[i])) err = 1;
+        }
+        free(b.ids);
+    }
+    cells_free(&c);
+    return err ? OR_E_NONFINITE : OR_OK;
+}
+
 int or_default_mass(const or_params *p, double m_out[2])
 {
     particle_masses(p, m_out);

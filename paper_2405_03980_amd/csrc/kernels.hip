@@ -1641,6 +1641,130 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t value, size_t n)
     if (i < n) p[i] = value;
 }
 
+
+// ------------------------------------------------------------ vortex diagnostic -----
+// The paper counts spinning vortices by image analysis of the rotational-force intensity
+// (the fifth term of Eq. 2, 2 eta_r curl(omega_0)) on the z = 0 section (Sec. 3).  Here:
+// the intensity of each fluid particle in the section -dx <= z - z0 < dx (z periodic) is
+// I = |sum over viscous neighbours j of 2 eta V_j F_ij (w_i + w_j) x r_ij| in FP64 (the
+// spin part of the viscous pair force per unit volume); a pixel of side dx holds the
+// largest intensity of its particles; pixels with a positive value of at least theta
+// times the largest are on; 8-connected sets of on pixels are labelled by their smallest
+// pixel index; components of at least min_pixels pixels are counted.
+
+template <typename R>
+__global__ void k_vortex_intensity(DevState s, VortexArgs a, unsigned long long *img,
+                                   unsigned long long *vmax)
+{
+#pragma clang fp contract(off)
+    PIdx t = map_thread(s);
+    if (!t.active) return;
+    const InstDesc *d = t.d;
+    const uint32_t p = t.p, N = s.N;
+    const int cur = s.cur;
+    const double *X = s.x[cur], *Wv = s.w[cur];
+    const uint8_t *SK = s.sk[cur];
+    if ((SK[p] >> 1) != KIND_FLUID) return;
+    const double xi0 = X[p], xi1 = X[N + p], xi2 = X[2 * N + p];
+    double dz = xi2 - a.z0;
+    dz = dz - a.Lz * floor(dz / a.Lz + 0.5);
+    if (!(dz >= -a.dx && dz < a.dx)) return;
+    // spins at the end of the step: the closing half kick is still pending for fluid
+    // particles (as in k_read); walls hold their exact spin
+    const R *AL = (const R *)s.alpha;
+    auto spin = [&](uint32_t q, int c) {
+        const double pk = (SK[q] >> 1) == KIND_FLUID ? a.pend : 0.0;
+        return __fma_rn(pk, (double)AL[c * N + q], Wv[c * N + q]);
+    };
+    const double wi0 = spin(p, 0), wi1 = spin(p, 1), wi2 = spin(p, 2);
+    const R *RP = (const R *)s.rhoP;
+    const double m1 = d->mass[1], eta2 = 2.0 * d->eta, cut2 = d->cut2;
+    const uint32_t cxyz = s.cell_xyz[s.pcell[p]];
+    uint32_t err = 0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for_each_cell(s, d, cxyz & 1023, (cxyz >> 10) & 1023, cxyz >> 20, err,
+                  [&](uint32_t b, uint32_t e) {
+        for (uint32_t q = b; q < e; ++q) {
+            if ((SK[q] & 1) != 1 || q == p) continue;
+            const double r0 = min_img(d, 0, xi0 - X[q]), r1 = min_img(d, 1, xi1 - X[N + q]),
+                         r2 = min_img(d, 2, xi2 - X[2 * N + q]);
+            const double rr2 = r2_exact(r0, r1, r2);
+            if (!(rr2 < cut2)) continue;
+            double Wk, Fk;
+            kernel_WF<double>(d->kernel, rr2, d->inv_h, d->wnorm, Wk, Fk);
+            const double g = eta2 * (m1 / (double)RP[2 * q]) * Fk;
+            const double w0 = wi0 + spin(q, 0), w1 = wi1 + spin(q, 1), w2 = wi2 + spin(q, 2);
+            s0 += g * (w1 * r2 - w2 * r1);
+            s1 += g * (w2 * r0 - w0 * r2);
+            s2 += g * (w0 * r1 - w1 * r0);
+        }
+    });
+    const double I = sqrt(s0 * s0 + s1 * s1 + s2 * s2);
+    if (!isfinite(I)) err |= ERR_NONFINITE;
+    int ix = (int)floor((xi0 - a.lox) / a.dx), iy = (int)floor((xi1 - a.loy) / a.dx);
+    ix = min(max(ix, 0), a.nx - 1);
+    iy = min(max(iy, 0), a.ny - 1);
+    if (isfinite(I)) {
+        // non-negative doubles order like their bit patterns
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(I);
+        atomicMax(&img[(size_t)iy * a.nx + ix], bits);
+        atomicMax(vmax, bits);
+    }
+    if (err) atomicOr(s.err, err);
+}
+
+__global__ void k_vortex_label_init(const unsigned long long *img, const unsigned long long *vmax,
+                                    double theta, uint32_t n, int32_t *lab)
+{
+#pragma clang fp contract(off)
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double v = __longlong_as_double((long long)img[i]);
+    const double thr = theta * __longlong_as_double((long long)*vmax);
+    lab[i] = (v > 0.0 && v >= thr) ? (int32_t)i : -1;
+}
+
+// One relaxation: every on pixel takes the smallest label among itself and its on
+// 8-neighbours, then follows its label's own label while that decreases (labels only
+// ever decrease and always name a pixel of the same component).
+__global__ void k_vortex_relax(int32_t *lab, int nx, int ny, uint32_t *changed)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nx * ny) return;
+    const int l0 = lab[i];
+    if (l0 < 0) return;
+    const int iy = i / nx, ix = i - iy * nx;
+    int m = l0;
+    for (int dy = -1; dy <= 1; dy++) {
+        const int y = iy + dy;
+        if (y < 0 || y >= ny) continue;
+        for (int dx = -1; dx <= 1; dx++) {
+            const int x = ix + dx;
+            if (x < 0 || x >= nx) continue;
+            const int l = lab[y * nx + x];
+            if (l >= 0 && l < m) m = l;
+        }
+    }
+    for (int l = lab[m]; l >= 0 && l < m; l = lab[m]) m = l;
+    if (m < l0) {
+        atomicMin(&lab[i], m);
+        *changed = 1u;
+    }
+}
+
+__global__ void k_vortex_sizes(const int32_t *lab, uint32_t n, int32_t *size)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && lab[i] >= 0) atomicAdd(&size[lab[i]], 1);
+}
+
+__global__ void k_vortex_count(const int32_t *lab, const int32_t *size, uint32_t n,
+                               int32_t min_pixels, int32_t *count)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && lab[i] == (int32_t)i && size[i] >= min_pixels) atomicAdd(count, 1);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launchers ---------
@@ -1737,6 +1861,39 @@ hipError_t launch_debug_nbr(const DevState &d, const Launch &L, hipStream_t st, 
                             int64_t *row_ptr, int32_t *cols)
 {
     k_debug_nbr<<<grid_for(d.n_waves, L.bs_stream), L.bs_stream, 0, st>>>(d, phase, row_ptr, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_vortex_intensity(const DevState &d, const Launch &L, hipStream_t st,
+                                   const VortexArgs &a, unsigned long long *img,
+                                   unsigned long long *vmax)
+{
+    unsigned g = grid_for(d.n_waves, L.bs_stream);
+    if (d.precision == 0) k_vortex_intensity<double><<<g, L.bs_stream, 0, st>>>(d, a, img, vmax);
+    else k_vortex_intensity<float><<<g, L.bs_stream, 0, st>>>(d, a, img, vmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_vortex_label_init(hipStream_t st, const unsigned long long *img,
+                                    const unsigned long long *vmax, double theta, uint32_t n,
+                                    int32_t *lab)
+{
+    k_vortex_label_init<<<(n + 255) / 256, 256, 0, st>>>(img, vmax, theta, n, lab);
+    return hipGetLastError();
+}
+
+hipError_t launch_vortex_relax(hipStream_t st, int32_t *lab, int nx, int ny, uint32_t *changed)
+{
+    const unsigned n = (unsigned)(nx * ny);
+    k_vortex_relax<<<(n + 255) / 256, 256, 0, st>>>(lab, nx, ny, changed);
+    return hipGetLastError();
+}
+
+hipError_t launch_vortex_count(hipStream_t st, const int32_t *lab, int32_t *size, uint32_t n,
+                               int32_t min_pixels, int32_t *count)
+{
+    k_vortex_sizes<<<(n + 255) / 256, 256, 0, st>>>(lab, n, size);
+    k_vortex_count<<<(n + 255) / 256, 256, 0, st>>>(lab, size, n, min_pixels, count);
     return hipGetLastError();
 }
 

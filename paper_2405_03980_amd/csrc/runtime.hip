@@ -5,6 +5,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <new>
 #include <string>
@@ -339,6 +341,7 @@ struct sph_batch {
     hipStream_t stream = nullptr;
     int n_inst = 0;
     std::vector<InstDesc> desc;
+    std::vector<sph_params> params;  // as given at creation
     std::vector<StepParams> steptab;
     bool loaded = false;
     double pending_dt = 0.0;  // closing half kick of this dt still to apply
@@ -522,7 +525,15 @@ sph_status batch_step(sph_batch *b, double dt, const double *Omega, int32_t nste
     return SPH_OK;
 }
 
+// Pixel grid of the vortex image: squares of side dx over the x-y extent of the domain.
+void vortex_grid(const sph_params &p, int32_t &nx, int32_t &ny)
+{
+    nx = (int32_t)std::ceil((p.hi[0] - p.lo[0]) / p.dx - 1e-9);
+    ny = (int32_t)std::ceil((p.hi[1] - p.lo[1]) / p.dx - 1e-9);
+}
+
 }  // namespace
+
 
 // ------------------------------------------------------------ C ABI -----------------
 
@@ -607,6 +618,7 @@ sph_status sph_batch_create(int32_t n_inst, const sph_params *params, const int6
     b->stream = (hipStream_t)hip_stream;
     b->n_inst = n_inst;
     b->desc = pl.desc;
+    b->params.assign(params, params + n_inst);
     b->steptab.assign(n_inst, StepParams{1.0, 0.0, 0.0, 0.0});
     Carver c2;
     c2.base = (char *)workspace;
@@ -858,6 +870,68 @@ sph_status sph_sync(sph_sim *s)
 {
     if (!s) return SPH_E_INVALID;
     return batch_sync(s->b);
+}
+
+sph_status sph_vortex_dims(const sph_params *p, int32_t *nx, int32_t *ny)
+{
+    if (!p || !nx || !ny) return SPH_E_INVALID;
+    std::string msg;
+    sph_status st = validate(p, msg);
+    if (st != SPH_OK) return st;
+    vortex_grid(*p, *nx, *ny);
+    return SPH_OK;
+}
+
+sph_status sph_vortex_image(sph_sim *s, double z0, double theta, int32_t min_pixels,
+                            double *image, int32_t *labels, int32_t *scratch, int32_t *count)
+{
+    if (!s) return SPH_E_INVALID;
+    sph_batch *b = s->b;
+    if (!image || !labels || !scratch || !count || !std::isfinite(z0) || !std::isfinite(theta) ||
+        theta < 0.0 || min_pixels < 1 || ((uintptr_t)scratch & 7u)) {
+        b->err = "vortex image: needs image, labels, 8-byte aligned scratch and count, finite z0, "
+                 "theta >= 0 and min_pixels >= 1";
+        return SPH_E_INVALID;
+    }
+    if (!b->loaded) { b->err = "vortex image before init"; return SPH_E_STATE; }
+    const sph_params &p = b->params[0];
+    int32_t nx, ny;
+    vortex_grid(p, nx, ny);
+    const uint32_t n = (uint32_t)nx * (uint32_t)ny;
+    VortexArgs a;
+    a.z0 = z0;
+    a.Lz = p.hi[2] - p.lo[2];
+    a.dx = p.dx;
+    a.lox = p.lo[0];
+    a.loy = p.lo[1];
+    a.pend = 0.5 * b->pending_dt;
+    a.nx = nx;
+    a.ny = ny;
+    // scratch: size[n] | changed | count | (8-byte aligned) image maximum
+    int32_t *size = scratch;
+    uint32_t *changed = (uint32_t *)(scratch + n);
+    int32_t *cnt = scratch + n + 1;
+    unsigned long long *vmax = (unsigned long long *)(scratch + ((n + 3) & ~1u));
+    unsigned long long *img = (unsigned long long *)image;
+    hipError_t e = launch_fill_u32((uint32_t *)image, 0u, 2 * (size_t)n, b->stream);
+    if (e == hipSuccess) e = launch_fill_u32((uint32_t *)scratch, 0u, ((n + 3) & ~1u) + 2, b->stream);
+    if (e == hipSuccess) e = launch_vortex_intensity(b->ds, b->L, b->stream, a, img, vmax);
+    if (e == hipSuccess) e = launch_vortex_label_init(b->stream, img, vmax, theta, n, labels);
+    if (e != hipSuccess) return hip_fail(e, b->err, "vortex image");
+    // relax until a pass changes nothing (labels only decrease, so at most n passes)
+    for (uint32_t it = 0; it <= n; it++) {
+        uint32_t flag = 0;
+        e = launch_fill_u32(changed, 0u, 1, b->stream);
+        if (e == hipSuccess) e = launch_vortex_relax(b->stream, labels, nx, ny, changed);
+        if (e == hipSuccess) e = hipMemcpyAsync(&flag, changed, sizeof(flag), hipMemcpyDeviceToHost, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return hip_fail(e, b->err, "vortex labels");
+        if (!flag) break;
+    }
+    e = launch_vortex_count(b->stream, labels, size, n, min_pixels, cnt);
+    if (e == hipSuccess) e = hipMemcpyAsync(count, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, b->stream);
+    if (e != hipSuccess) return hip_fail(e, b->err, "vortex count");
+    return batch_sync(b);
 }
 
 const char *sph_last_error(const sph_sim *s)

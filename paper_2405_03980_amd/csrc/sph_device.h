@@ -110,4 +110,20 @@ hipError_t launch_debug_nbr(const DevState &d, const Launch &L, hipStream_t st, 
                             int64_t *row_ptr, int32_t *cols);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st);
 
+// Vortex diagnostic of one instance (the first): section z0, pixel grid nx x ny of side
+// dx from (lox, loy), z period Lz; pend = half the last step's dt (the pending half kick).
+struct VortexArgs {
+    double z0, Lz, dx, lox, loy, pend;
+    int32_t nx, ny;
+};
+hipError_t launch_vortex_intensity(const DevState &d, const Launch &L, hipStream_t st,
+                                   const VortexArgs &a, unsigned long long *img,
+                                   unsigned long long *vmax);
+hipError_t launch_vortex_label_init(hipStream_t st, const unsigned long long *img,
+                                    const unsigned long long *vmax, double theta, uint32_t n,
+                                    int32_t *lab);
+hipError_t launch_vortex_relax(hipStream_t st, int32_t *lab, int nx, int ny, uint32_t *changed);
+hipError_t launch_vortex_count(hipStream_t st, const int32_t *lab, int32_t *size, uint32_t n,
+                               int32_t min_pixels, int32_t *count);
+
 }  // namespace sph

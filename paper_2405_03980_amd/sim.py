@@ -151,6 +151,28 @@ class Simulation:
         _check(st, "sph_debug_neighbors", self._err)
         return row.cpu().numpy(), cols[: nnz.value].cpu().numpy()
 
+    def vortex_image(self, z0: float = 0.0, theta: float = 0.5, min_pixels: int = 4,
+                     to_numpy: bool = True):
+        """(count, image [ny, nx], labels [ny, nx]) of the rotational-force intensity on the
+        section z = z0 (sph_vortex_image)."""
+        nx, ny = C.c_int32(), C.c_int32()
+        _check(self.lib.sph_vortex_dims(C.byref(self.params), C.byref(nx), C.byref(ny)),
+               "sph_vortex_dims")
+        nx, ny = int(nx.value), int(ny.value)
+        with torch.cuda.stream(self.stream):
+            img = torch.empty((ny, nx), dtype=torch.float64, device=self.device)
+            lab = torch.empty((ny, nx), dtype=torch.int32, device=self.device)
+            scratch = torch.empty(nx * ny + 8, dtype=torch.int32, device=self.device)
+        cnt = C.c_int32()
+        _check(self.lib.sph_vortex_image(self._h, C.c_double(z0), C.c_double(theta),
+                                         C.c_int32(min_pixels), C.c_void_p(img.data_ptr()),
+                                         C.c_void_p(lab.data_ptr()),
+                                         C.c_void_p(scratch.data_ptr()), C.byref(cnt)),
+               "sph_vortex_image", self._err)
+        if to_numpy:
+            return int(cnt.value), img.cpu().numpy(), lab.cpu().numpy()
+        return int(cnt.value), img, lab
+
     def set_tuning(self, block_density=0, block_force=0, block_stream=0, use_graph=-1, sweep=0):
         t = L.SphTuning(block_density, block_force, block_stream, use_graph, sweep)
         _check(self.lib.sph_set_tuning(self._h, C.byref(t)), "sph_set_tuning", self._err)
