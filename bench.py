@@ -214,7 +214,7 @@ def main():
     n, nf = w.n, w.n_fluid
     print(f"[bench] {name}: {n} particles ({nf} fluid)", file=sys.stderr, flush=True)
 
-    def run(precision, steps, warmup, tuning):
+    def run(precision, steps, warmup, tuning, vortex=False):
         tun, cf = tuning
         s = S.Simulation(dict(w.params, cell_factor=cf), w.n, precision=precision)
         if tun:
@@ -231,13 +231,25 @@ def main():
         elapsed = time.perf_counter() - t0
         s.sync()
         fields = s.read(("rho", "P", "v", "omega", "acc"))
+        if vortex:
+            # the vortex diagnostic of the z = 0 section on the state just stepped
+            s.vortex_image(0.0, 0.5, 3, to_numpy=False)  # warm-up
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            cnt, img, _ = s.vortex_image(0.0, 0.5, 3, to_numpy=False)
+            torch.cuda.synchronize()
+            fields["vortex"] = {"ms": round(1e3 * (time.perf_counter() - t1), 3), "z0": 0.0,
+                                "theta": 0.5, "min_pixels": 3, "count": cnt,
+                                "image": [int(img.shape[0]), int(img.shape[1])]}
         s.close()
         del s
         torch.cuda.empty_cache()
         return elapsed, ms, nsteps, fields
 
     tuning = load_tuning(args.tuning, name)
-    elapsed, ms, nsteps, f_mixed = run(L.FP32_MIXED, args.steps, args.warmup, tuning)
+    elapsed, ms, nsteps, f_mixed = run(L.FP32_MIXED, args.steps, args.warmup, tuning, vortex=True)
+    vortex = f_mixed.pop("vortex")
+    print(f"[bench] vortex diagnostic: {vortex}", file=sys.stderr, flush=True)
     assert nsteps == args.steps
     ms_step = 1e3 * elapsed / args.steps
     value = n * args.steps / elapsed
@@ -299,6 +311,7 @@ def main():
         "roofline": roof,
         "fp64_gpu": fp64,
         "batch64": batch,
+        "vortex_diag": vortex,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -7,6 +7,7 @@ sampled particles against the oracle evaluated one by one, one full step of ever
 particle, and 100 steps of the FP32-mixed path against the FP64 path.  64-instance batch:
 every instance against its own single-instance run.
 """
+import copy
 import json
 import os
 
@@ -91,6 +92,41 @@ def cyl1957():
     w = I.config(3)
     print(f"[full] cylinder 19.57M: n={w.n}", flush=True)
     return w
+
+
+def test_cylinder_19p57M_vortex_image(cyl1957):
+    """The vortex diagnostic of the z = 0 section at full size, in the benchmarked launch
+    configuration, with random spins on the fluid: the oracle evaluates the density of the
+    particles within dx + 2h of the section, then the section's intensities (any density
+    read outside that slab is NaN and would show), the image and its components."""
+    from oracle import vortex as V
+    w = cyl1957
+    omega = w.omega + np.random.default_rng(12).normal(size=w.omega.shape) * (w.kind == I.FLUID)
+    theta, min_pixels = 0.5, 3
+    wv = copy.copy(w)
+    wv.omega = omega
+    s = _sim(wv, L.FP32_MIXED, "cylinder_nz184")
+    cnt, img, lab = s.vortex_image(0.0, theta, min_pixels)
+    s.close()
+    p = w.params
+    dz = w.x[2] - 1.0 * np.floor(w.x[2] + 0.5)
+    near = np.flatnonzero(np.abs(dz) < p["dx"] + 2.0 * p["h"] + 1e-12)
+    rho_near = O.eval_subset(p, w.x, w.v, omega, w.species, w.kind, near)[0]
+    rho = np.full(w.n, np.nan)
+    rho[near] = rho_near
+    sel = V.section_mask(p, w.x, w.kind, 0.0)
+    inten = O.rot_intensity(p, w.x, omega, w.species, w.kind, rho, mask=sel)
+    oimg = V.plane_image(p, w.x, w.kind, inten, 0.0)
+    vmax = oimg.max()
+    err = np.abs(img - oimg).max() / vmax
+    print(f"19.57M vortex image: {img.shape}, section {sel.sum()} particles, err {err:.2e}, "
+          f"components {cnt}", flush=True)
+    assert np.isfinite(oimg).all() and err < 1e-5
+    on = lab >= 0
+    clear = np.abs(oimg - theta * vmax) > 2e-5 * vmax
+    assert np.array_equal(on[clear], V.threshold(oimg, theta)[clear])
+    assert np.array_equal(lab, V.components(on))
+    assert cnt == V.count(lab, min_pixels) and cnt > 0
 
 
 def test_cylinder_19p57M_sampled_initial_fields(cyl1957):
