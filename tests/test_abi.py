@@ -112,6 +112,21 @@ def test_grid_dims_agree_with_oracle(case):
     assert list(dims) == list(on)
 
 
+@pytest.mark.parametrize("nz", [19, 92, 184])
+def test_vortex_dims_agree_with_oracle(nz):
+    """The vortex image grid (host only): square pixels of side dx over the x-y extent."""
+    from oracle import vortex as V
+    w = I.make_cylinder(nz) if nz != 19 else I.config(0)
+    nx, ny = C.c_int32(), C.c_int32()
+    assert L.lib().sph_vortex_dims(C.byref(L.make_params(w.params)), C.byref(nx), C.byref(ny)) == L.OK
+    assert (nx.value, ny.value) == V.image_dims(w.params)
+    if nz != 19:
+        assert nx.value == ny.value == 2 * nz
+    assert L.lib().sph_vortex_dims(C.byref(L.make_params(w.params)), None, C.byref(ny)) == L.E_INVALID
+    bad = L.make_params(dict(w.params, dx=-1.0))
+    assert L.lib().sph_vortex_dims(C.byref(bad), C.byref(nx), C.byref(ny)) == L.E_INVALID
+
+
 def test_create_rejects_missing_workspace():
     w = I.make_cylinder(10)
     p = _params(w)
