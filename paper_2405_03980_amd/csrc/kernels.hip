@@ -1119,7 +1119,8 @@ __device__ __forceinline__ void hit_share(Word &&word, uint32_t H, int g, int G,
 
 // Ballot tests of targets kbase .. kbase + ntc - 1 (staged indices) against the first NWc
 // candidate windows, NWc fixed at compile time so that the windows need no branch per
-// target.  Lane t ORs target t's masks into mlo/mhi (low and high halves).
+// target.  The ballots of one target stay in scalar registers until lane t copies them
+// into mlo/mhi (low and high halves) in one masked pass.
 // The test is |c - t|^2 < cut2 expanded as |c|^2 - 2 c.t < cut2 - |t|^2, with the
 // candidate's -2c (px, py, pz) and |c|^2 (cc) precomputed: three FMAs and a compare per
 // target and window.  Positions are relative to the brick centre in units of h
@@ -1128,21 +1129,20 @@ __device__ __forceinline__ void hit_share(Word &&word, uint32_t H, int g, int G,
 template <int NWc>
 __device__ __forceinline__ void test_targets(const float4 *stage, const float *px, const float *py,
                                              const float *pz, const float *cc, uint32_t kbase,
-                                             uint32_t ntc, float cut2, int lane, uint32_t *mlo,
-                                             uint32_t *mhi)
+                                             uint32_t ntc, float cut2, int lane, uint64_t *mw)
 {
     for (uint32_t t = 0; t < ntc; t++) {
         const float4 T = stage[kbase + t];
         const float thr = cut2 - (T.x * T.x + T.y * T.y + T.z * T.z);
-        uint32_t mine = (uint32_t)lane == t ? ~0u : 0u;
-        asm volatile("" : "+v"(mine));  // an opaque lane mask, so that the updates below
-                                        // stay one and-or instead of becoming selects
+        uint64_t m[NWc];
 #pragma unroll
         for (int c = 0; c < NWc; c++) {
             const float e = fmaf(pz[c], T.z, fmaf(py[c], T.y, fmaf(px[c], T.x, cc[c])));
-            const uint64_t m = __ballot(e < thr);
-            mlo[c] |= mine & (uint32_t)m;
-            mhi[c] |= mine & (uint32_t)(m >> 32);
+            m[c] = __ballot(e < thr);
+        }
+        if ((uint32_t)lane == t) {
+#pragma unroll
+            for (int c = 0; c < NWc; c++) mw[c] = m[c];
         }
     }
 }
@@ -1208,42 +1208,37 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
             const uint32_t ntc = min((uint32_t)kListTargets, nt - t0);
             // test: one target at a time against every window; lane t collects target t's
             // masks
-            uint32_t mlo[kCandWin], mhi[kCandWin];
+            uint64_t mw[kCandWin];
 #pragma unroll
-            for (int c = 0; c < kCandWin; c++) mlo[c] = mhi[c] = 0u;
+            for (int c = 0; c < kCandWin; c++) mw[c] = 0ull;
             switch (S.NW) {
-            case 1: test_targets<1>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-            case 2: test_targets<2>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-            case 3: test_targets<3>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-            case 4: test_targets<4>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-            case 5: test_targets<5>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-            case 6: test_targets<6>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-            case 7: test_targets<7>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-            case 8: test_targets<8>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-            case 9: test_targets<9>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mlo, mhi); break;
-            default: test_targets<10>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mlo, mhi); break;
+            case 1: test_targets<1>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mw); break;
+            case 2: test_targets<2>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mw); break;
+            case 3: test_targets<3>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mw); break;
+            case 4: test_targets<4>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mw); break;
+            case 5: test_targets<5>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mw); break;
+            case 6: test_targets<6>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mw); break;
+            case 7: test_targets<7>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mw); break;
+            case 8: test_targets<8>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mw); break;
+            case 9: test_targets<9>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mw); break;
+            default: test_targets<10>(stage, px, py, pz, cc, toff + t0, ntc, cut2, lane, mw); break;
             }
             static_assert(kCandWin == 10, "one case per window count");
             // a target is not its own neighbour: its lane clears the bit of its list position
             if ((uint32_t)lane < ntc) {
                 const uint32_t vs = stencil_self(S, toff + t0 + (uint32_t)lane);
-                const uint32_t keep = ~(1u << (vs & 31));
+                const uint64_t keep = ~(1ull << (vs & 63));
 #pragma unroll
-                for (int c = 0; c < kCandWin; c++) {
-                    if ((vs >> 6) == (uint32_t)c) {
-                        if (vs & 32) mhi[c] &= keep;
-                        else mlo[c] &= keep;
-                    }
-                }
+                for (int c = 0; c < kCandWin; c++)
+                    if ((vs >> 6) == (uint32_t)c) mw[c] &= keep;
             }
             if ((uint32_t)lane < ntc) {
                 uint64_t *gm = s.masks + (size_t)(pbase + t0 + lane) * kMaskSlots;
 #pragma unroll
                 for (int c = 0; c < kCandWin; c++) {
                     if (c < (int)S.NW) {
-                        const uint64_t m = ((uint64_t)mhi[c] << 32) | mlo[c];
-                        msk[w][lane][c] = m;
-                        gm[c] = m;
+                        msk[w][lane][c] = mw[c];
+                        gm[c] = mw[c];
                     }
                 }
             }
