@@ -918,15 +918,21 @@ sph_status sph_vortex_image(sph_sim *s, double z0, double theta, int32_t min_pix
     if (e == hipSuccess) e = launch_vortex_intensity(b->ds, b->L, b->stream, a, img, vmax);
     if (e == hipSuccess) e = launch_vortex_label_init(b->stream, img, vmax, theta, n, labels);
     if (e != hipSuccess) return hip_fail(e, b->err, "vortex image");
-    // relax until a pass changes nothing (labels only decrease, so at most n passes)
-    for (uint32_t it = 0; it <= n; it++) {
+    // Relax until a pass changes nothing.  Each pass carries a component's smallest label
+    // at least one pixel further, so diameter + 1 <= n passes end it.
+    bool settled = false;
+    for (uint32_t it = 0; it <= n && !settled; it++) {
         uint32_t flag = 0;
         e = launch_fill_u32(changed, 0u, 1, b->stream);
         if (e == hipSuccess) e = launch_vortex_relax(b->stream, labels, nx, ny, changed);
         if (e == hipSuccess) e = hipMemcpyAsync(&flag, changed, sizeof(flag), hipMemcpyDeviceToHost, b->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
         if (e != hipSuccess) return hip_fail(e, b->err, "vortex labels");
-        if (!flag) break;
+        settled = flag == 0;
+    }
+    if (!settled) {
+        b->err = "vortex labels did not settle";
+        return SPH_E_STATE;
     }
     e = launch_vortex_count(b->stream, labels, size, n, min_pixels, cnt);
     if (e == hipSuccess) e = hipMemcpyAsync(count, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, b->stream);
