@@ -1647,9 +1647,9 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t value, size_t n)
 // times the largest are on; 8-connected sets of on pixels are labelled by their smallest
 // pixel index; components of at least min_pixels pixels are counted.
 
+// One thread per particle; threads of particles outside the section leave at once.
 template <typename R>
-__global__ void k_vortex_intensity(DevState s, VortexArgs a, unsigned long long *img,
-                                   unsigned long long *vmax)
+__global__ void k_vortex_intensity(DevState s, VortexArgs a, unsigned long long *img)
 {
 #pragma clang fp contract(off)
     PIdx t = map_thread(s);
@@ -1703,9 +1703,26 @@ __global__ void k_vortex_intensity(DevState s, VortexArgs a, unsigned long long 
         // non-negative doubles order like their bit patterns
         const unsigned long long bits = (unsigned long long)__double_as_longlong(I);
         atomicMax(&img[(size_t)iy * a.nx + ix], bits);
-        atomicMax(vmax, bits);
     }
     if (err) atomicOr(s.err, err);
+}
+
+// Largest pixel value (one block; max is exact in any order).
+__global__ void k_vortex_max(const unsigned long long *img, uint32_t n, unsigned long long *vmax)
+{
+    __shared__ unsigned long long part[1024 / 64];
+    unsigned long long m = 0;
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) m = img[i] > m ? img[i] : m;
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(m, off);
+        m = o > m ? o : m;
+    }
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (uint32_t w = 1; w < blockDim.x / 64; w++) m = part[w] > m ? part[w] : m;
+        *vmax = m;
+    }
 }
 
 __global__ void k_vortex_label_init(const unsigned long long *img, const unsigned long long *vmax,
@@ -1863,9 +1880,10 @@ hipError_t launch_vortex_intensity(const DevState &d, const Launch &L, hipStream
                                    const VortexArgs &a, unsigned long long *img,
                                    unsigned long long *vmax)
 {
-    unsigned g = grid_for(d.n_waves, L.bs_stream);
-    if (d.precision == 0) k_vortex_intensity<double><<<g, L.bs_stream, 0, st>>>(d, a, img, vmax);
-    else k_vortex_intensity<float><<<g, L.bs_stream, 0, st>>>(d, a, img, vmax);
+    const unsigned g = grid_for(d.n_waves, L.bs_stream);
+    if (d.precision == 0) k_vortex_intensity<double><<<g, L.bs_stream, 0, st>>>(d, a, img);
+    else k_vortex_intensity<float><<<g, L.bs_stream, 0, st>>>(d, a, img);
+    k_vortex_max<<<1, 1024, 0, st>>>(img, (uint32_t)(a.nx * a.ny), vmax);
     return hipGetLastError();
 }
 

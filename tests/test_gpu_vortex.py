@@ -48,7 +48,7 @@ def _compare(got, ref_img, ref_lab, ref_count, theta, min_pixels, tol):
 
 
 @pytest.mark.parametrize("prec", [FP64, MIXED])
-@pytest.mark.parametrize("z0,theta,min_pixels", [(0.0, 0.5, 2), (0.37, 0.3, 4)])
+@pytest.mark.parametrize("z0,theta,min_pixels", [(0.0, 0.5, 2), (0.37, 0.3, 4), (-2.63, 0.4, 2)])
 def test_vortex_image_matches_oracle(prec, z0, theta, min_pixels):
     w = _cylinder(24, 5)
     print(f"[vortex] prec={prec} z0={z0} theta={theta} n={w.n}", flush=True)
