@@ -642,9 +642,10 @@ __global__ void k_force(DevState s)
 // One workgroup per brick of 2x2x2 cells (edge >= 2h each).  The 4x4x4 cells around the
 // brick (its neighbourhood, periodic images shifted into the brick's frame) are staged in
 // LDS in slot order, x fastest, so the 27-cell stencil of a target cell is 9 contiguous
-// runs ("rows").  Wave w serves brick cell w.  Positions are staged in single precision
-// relative to the brick centre (FP32-mixed path); neighbourhoods too large to stage fall
-// back to the per-particle code.
+// runs ("rows").  Wave w serves brick cell w.  Positions and velocities are staged in
+// single precision relative to the brick centre (and to one particle's velocity), in units
+// of h (FP32-mixed path); neighbourhoods too large to stage fall back to the per-particle
+// code.
 
 constexpr int kBrickThreads = 512;
 constexpr int kStageDensity = 2048;
