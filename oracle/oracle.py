@@ -43,6 +43,8 @@ class Params(C.Structure):
         ("mass", C.c_double * 2),
         ("eta", C.c_double), ("sigma_T", C.c_double), ("C_l", C.c_double),
         ("kappa_I", C.c_double),
+        ("pressure_filter", C.c_int32), ("pad2", C.c_int32),
+        ("coll_alpha", C.c_double), ("coll_e", C.c_double),
     ]
 
 
@@ -55,6 +57,8 @@ def params_from(d: dict) -> Params:
     p.rho0, p.c0, p.gamma = d["rho0"], d["c0"], d["gamma"]
     p.mass[0], p.mass[1] = d["mass"][0], d["mass"][1]
     p.eta, p.sigma_T, p.C_l, p.kappa_I = d["eta"], d["sigma_T"], d["C_l"], d["kappa_I"]
+    p.pressure_filter = int(d.get("pressure_filter", 0))
+    p.coll_alpha, p.coll_e = float(d.get("coll_alpha", 0.0)), float(d.get("coll_e", 0.0))
     return p
 
 
@@ -79,7 +83,7 @@ def lib():
         L.or_num_threads.restype = C.c_int
         for name in ("or_cells", "or_density", "or_forces", "or_evaluate", "or_step",
                      "or_diagnostics", "or_default_mass", "or_grid_dims", "or_eval_subset",
-                     "or_rot_intensity"):
+                     "or_rot_intensity", "or_pressure_filter", "or_collide"):
             getattr(L, name).restype = C.c_int
         _ = (dp, pp)
         _lib = L
@@ -229,6 +233,32 @@ def forces(params, x, v, omega, species, kind, rho, P, S, brute=False):
                            _p(_c(kind, np.uint8)), _p(_c(rho, np.float64)), _p(_c(P, np.float64)),
                            _p(_c(S, np.float64)), C.c_int(int(brute)), _p(acc), _p(alpha)))
     return acc, alpha
+
+
+def pressure_filter(params, x, species, kind, rho, P, brute=False):
+    """Filtered pressure from given rho and P fields (Shepard average over the particle
+    and its fluid and inner-wall neighbours; outer walls keep theirs)."""
+    x = _c(x, np.float64)
+    n = x.shape[1]
+    out = np.zeros(n)
+    p = params_from(params)
+    _check(lib().or_pressure_filter(C.byref(p), C.c_int64(n), _p(x), _p(_c(species, np.uint8)),
+                                    _p(_c(kind, np.uint8)), _p(_c(rho, np.float64)),
+                                    _p(_c(P, np.float64)), C.c_int(int(brute)), _p(out)))
+    return out
+
+
+def collide(params, x, v, species, kind, brute=False):
+    """Velocities after the collision step (pairs closer than coll_alpha dx that approach
+    each other leave with restitution coll_e; walls are unchanged)."""
+    x = _c(x, np.float64)
+    n = x.shape[1]
+    out = np.zeros((3, n))
+    p = params_from(params)
+    _check(lib().or_collide(C.byref(p), C.c_int64(n), _p(x), _p(_c(v, np.float64)),
+                            _p(_c(species, np.uint8)), _p(_c(kind, np.uint8)),
+                            C.c_int(int(brute)), _p(out)))
+    return out
 
 
 def eval_subset(params, x, v, omega, species, kind, idx):

@@ -22,6 +22,8 @@
  *     (Sec. 2.1);
  *   - wall and dummy particles: inner wall layer gets summed density/pressure, outer
  *     layers keep their initial density and pressure (Sec. 3);
+ *   - optional pressure filter and collision step of Algorithm 1, in this project's
+ *     reading (the paper cites both models without their formulas);
  *   - velocity Verlet time integration (Sec. 2.3, Algorithm 1);
  *   - neighbour search by a cell-linked list (Sec. 2.3).
  */
@@ -49,6 +51,10 @@ typedef struct {
     double rho0, c0, gamma;
     double mass[2];
     double eta, sigma_T, C_l, kappa_I;
+    int32_t pressure_filter;   /* 0: none, 1: Shepard average of P (Algorithm 1)          */
+    int32_t pad2;
+    double coll_alpha;         /* collision distance / dx; 0: no collision step           */
+    double coll_e;             /* restitution of the collision step, in [0, 1]            */
 } or_params;
 
 /* ------------------------------------------------------------------------------------
@@ -145,6 +151,9 @@ static int make_grid(const or_params *p, grid_t *g)
     if (!(p->h > 0.0) || !(p->dx > 0.0) || p->cell_factor < 1 || p->cell_factor > 4) return OR_E_INVALID;
     if (p->gamma != 7.0) return OR_E_INVALID;
     double two_h = 2.0 * p->h;
+    if (p->pressure_filter != 0 && p->pressure_filter != 1) return OR_E_INVALID;
+    if (!(p->coll_alpha >= 0.0) || !(p->coll_alpha * p->dx < two_h)) return OR_E_INVALID;
+    if (!(p->coll_e >= 0.0 && p->coll_e <= 1.0)) return OR_E_INVALID;
     g->cf = p->cell_factor;
     for (int a = 0; a < 3; a++) {
         g->L[a] = p->hi[a] - p->lo[a];
@@ -473,6 +482,139 @@ int or_density(const or_params *p, int64_t n, const double *x, const uint8_t *sp
 }
 
 /* ------------------------------------------------------------------------------------
+ * Pressure filter (Algorithm 1: after the pressures, before the pressure-gradient
+ * forces).  The paper names the filter and cites its source without giving its formula;
+ * the reading here is a Shepard (normalised kernel) average of the pressure over the
+ * particle itself and its neighbours, weighted by volume:
+ *   P~_i = (V_i P_i W(0) + sum_{j in N(i), src} V_j P_j W_ij)
+ *        / (V_i W(0)     + sum_{j in N(i), src} V_j W_ij),     V = m / rho,
+ * for fluid and inner-wall particles (the ones whose pressure comes from the equation of
+ * state); the sources are the same two kinds.  Outer-wall particles keep their fixed
+ * pressure and are not sources: theirs is a boundary value, not a pressure state.
+ * Self term first, then neighbours in ascending id.  `mask` (may be NULL) restricts the
+ * targets; P is read for their neighbours.
+ * ---------------------------------------------------------------------------------- */
+static int filter_impl(const or_params *p, const cells_t *c, int64_t n, const double *x,
+                       const uint8_t *species, const uint8_t *kind, const double *rho,
+                       const double *P, int brute, const uint8_t *mask, double *Pout)
+{
+    double m[2];
+    particle_masses(p, m);
+    double W0 = or_W(p->kernel, p->h, 0.0);
+    int err = 0;
+#pragma omp parallel
+    {
+        nbuf_t b = {0, 0};
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t i = 0; i < n; i++) {
+            if (mask && !mask[i]) continue;
+            if (kind[i] == OR_WALL_OUTER) {
+                Pout[i] = P[i];
+                continue;
+            }
+            double Vi = m[species[i]] / rho[i];
+            double num = Vi * P[i] * W0, den = Vi * W0;
+            int64_t cnt = neighbours(p, c, n, x, i, brute, &b);
+            for (int64_t k = 0; k < cnt; k++) {
+                int64_t j = b.ids[k];
+                if (kind[j] == OR_WALL_OUTER) continue;
+                double r[3];
+                within(p, &c->g, n, x, i, j, r);
+                double rr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+                double w = or_W(p->kernel, p->h, rr);
+                double Vj = m[species[j]] / rho[j];
+                num += Vj * P[j] * w;
+                den += Vj * w;
+            }
+            Pout[i] = num / den;
+            if (!isfinite(Pout[i])) err = 1;
+        }
+        free(b.ids);
+    }
+    return err ? OR_E_NONFINITE : OR_OK;
+}
+
+int or_pressure_filter(const or_params *p, int64_t n, const double *x, const uint8_t *species,
+                       const uint8_t *kind, const double *rho, const double *P, int brute,
+                       double *Pout)
+{
+    cells_t c;
+    int st = cells_build(p, n, x, &c);
+    if (st) return st;
+    st = filter_impl(p, &c, n, x, species, kind, rho, P, brute, NULL, Pout);
+    cells_free(&c);
+    return st;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Collision step (Algorithm 1; a correction that keeps particles from coming closer than
+ * their volume allows; the paper cites the model without its formula).  Reading: every
+ * pair of particles closer than r_c = coll_alpha dx that is approaching (v_ij . r_ij < 0,
+ * r_ij = x_i - x_j, v_ij = v_i - v_j) exchanges an impulse along r_ij that leaves it
+ * receding with the fraction coll_e (restitution) of its approach speed, as an isolated
+ * two-body collision would:
+ *   v_i <- v_i - (1 + e) mu_ij (v_ij . r_ij) r_ij / |r_ij|^2,
+ *   mu_ij = m_j / (m_i + m_j) for a fluid partner, 1 for a wall partner (walls move as
+ *   imposed and are not changed).
+ * Every term uses the velocities before the step (all pairs at once), so the impulses of
+ * fluid pairs cancel in sum m v, and being central they cancel in sum m x × v too.
+ * Fluid particles only; pairs in ascending id; the distance test is the neighbour test's
+ * ((dx^2 + dy^2) + dz^2 < r_c^2 with r_c = coll_alpha * dx, squared once).
+ * ---------------------------------------------------------------------------------- */
+static int collide_impl(const or_params *p, const cells_t *c, int64_t n, const double *x,
+                        const double *v, const uint8_t *species, const uint8_t *kind,
+                        int brute, double *vout)
+{
+    double m[2];
+    particle_masses(p, m);
+    const double rc = p->coll_alpha * p->dx;
+    const double rc2 = rc * rc;
+    const double e1 = 1.0 + p->coll_e;
+    int err = 0;
+#pragma omp parallel
+    {
+        nbuf_t b = {0, 0};
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t i = 0; i < n; i++) {
+            for (int a = 0; a < 3; a++) vout[a * n + i] = v[a * n + i];
+            if (kind[i] != OR_FLUID) continue;
+            double dv[3] = {0, 0, 0};
+            int64_t cnt = neighbours(p, c, n, x, i, brute, &b);
+            for (int64_t k = 0; k < cnt; k++) {
+                int64_t j = b.ids[k];
+                double r[3];
+                within(p, &c->g, n, x, i, j, r);
+                double r2 = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
+                if (!(r2 < rc2)) continue;
+                double vn = 0.0;
+                for (int a = 0; a < 3; a++) vn += (v[a * n + i] - v[a * n + j]) * r[a];
+                if (!(vn < 0.0)) continue;
+                double mu = kind[j] == OR_FLUID ? m[species[j]] / (m[species[i]] + m[species[j]]) : 1.0;
+                double g = -e1 * mu * vn / r2;
+                for (int a = 0; a < 3; a++) dv[a] += g * r[a];
+            }
+            for (int a = 0; a < 3; a++) {
+                vout[a * n + i] = v[a * n + i] + dv[a];
+                if (!isfinite(vout[a * n + i])) err = 1;
+            }
+        }
+        free(b.ids);
+    }
+    return err ? OR_E_NONFINITE : OR_OK;
+}
+
+int or_collide(const or_params *p, int64_t n, const double *x, const double *v,
+               const uint8_t *species, const uint8_t *kind, int brute, double *vout)
+{
+    cells_t c;
+    int st = cells_build(p, n, x, &c);
+    if (st) return st;
+    st = collide_impl(p, &c, n, x, v, species, kind, brute, vout);
+    cells_free(&c);
+    return st;
+}
+
+/* ------------------------------------------------------------------------------------
  * Pair forces and torques on fluid particles (walls get zero: their motion is imposed).
  * For j in N(i), r = x_i - x_j (minimum image), F_ij = -W'(r)/r, V = m/rho,
  * Pi_h = diag(1,1,0), S = inviscid, N = viscous (walls count as N):
@@ -585,8 +727,9 @@ int or_forces(const or_params *p, int64_t n, const double *x, const double *v, c
     return st;
 }
 
-/* Density then forces at the current state: the evaluation that precedes the first
- * half-kick of velocity Verlet. */
+/* Density, EOS, the pressure filter (when enabled) and forces at the current state: the
+ * evaluation that precedes the first half-kick of velocity Verlet.  P returns the
+ * pressure the forces used (filtered, when the filter is enabled). */
 int or_evaluate(const or_params *p, int64_t n, const double *x, const double *v,
                 const double *w, const uint8_t *species, const uint8_t *kind, int brute,
                 double *rho, double *P, double *S, double *acc, double *alpha)
@@ -595,13 +738,21 @@ int or_evaluate(const or_params *p, int64_t n, const double *x, const double *v,
     int st = cells_build(p, n, x, &c);
     if (st) return st;
     st = density_impl(p, &c, n, x, species, kind, brute, NULL, rho, P, S);
+    if (!st && p->pressure_filter) {
+        double *Pf = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+        if (!Pf) { cells_free(&c); return OR_E_INVALID; }
+        st = filter_impl(p, &c, n, x, species, kind, rho, P, brute, NULL, Pf);
+        if (!st) memcpy(P, Pf, (size_t)n * sizeof(double));
+        free(Pf);
+    }
     if (!st) st = forces_impl(p, &c, n, x, v, w, species, kind, rho, P, S, brute, NULL, acc, alpha);
     cells_free(&c);
     return st;
 }
 
 /* Density/pressure/S and accelerations of a subset of particles, from the full state.
- * Densities are evaluated for the subset and all its neighbours (the forces need them). */
+ * Densities are evaluated for the subset and all its neighbours (the forces need them),
+ * and with the pressure filter for their neighbours too. */
 int or_eval_subset(const or_params *p, int64_t n, const double *x, const double *v,
                    const double *w, const uint8_t *species, const uint8_t *kind,
                    int64_t n_sub, const int64_t *idx, double *rho_s, double *P_s,
@@ -624,8 +775,28 @@ int or_eval_subset(const or_params *p, int64_t n, const double *x, const double 
         int64_t cnt = neighbours(p, &c, n, x, i, 0, &b);
         for (int64_t q = 0; q < cnt; q++) need[b.ids[q]] = 1;
     }
+    /* with the filter, the subset's neighbours need filtered pressures, which need the
+     * densities of their own neighbours: one more ring */
+    uint8_t *need2 = NULL;
+    double *Pf = NULL;
+    if (p->pressure_filter) {
+        need2 = (uint8_t *)malloc((size_t)n);
+        Pf = (double *)malloc((size_t)n * sizeof(double));
+        memcpy(need2, need, (size_t)n);
+        for (int64_t i = 0; i < n; i++) {
+            if (!need[i]) continue;
+            int64_t cnt = neighbours(p, &c, n, x, i, 0, &b);
+            for (int64_t q = 0; q < cnt; q++) need2[b.ids[q]] = 1;
+        }
+    }
     free(b.ids);
-    st = density_impl(p, &c, n, x, species, kind, 0, need, rho, P, S);
+    st = density_impl(p, &c, n, x, species, kind, 0, need2 ? need2 : need, rho, P, S);
+    if (!st && p->pressure_filter) {
+        st = filter_impl(p, &c, n, x, species, kind, rho, P, 0, need, Pf);
+        for (int64_t i = 0; i < n && !st; i++)
+            if (need[i]) P[i] = Pf[i];
+    }
+    free(need2); free(Pf);
     if (!st) st = forces_impl(p, &c, n, x, v, w, species, kind, rho, P, S, 0, sub, acc, alpha);
     for (int64_t k = 0; k < n_sub && !st; k++) {
         int64_t i = idx[k];
@@ -645,7 +816,9 @@ int or_eval_subset(const or_params *p, int64_t n, const double *x, const double 
  * current positions (from or_evaluate or a previous step).  Per step:
  *   fluid: v += dt/2 a, w += dt/2 alpha, x += dt v, wrap periodic axes into [lo, hi);
  *   walls: (x, y) rotated by Omega dt about the z axis, v = Omega z x r, w = Omega z;
- *   density, EOS and forces at the new positions with the half-step v and w;
+ *   the collision step on the half-step velocities at the new positions (when enabled);
+ *   density, EOS, pressure filter (when enabled) and forces at the new positions with
+ *   the half-step v and w;
  *   fluid: v += dt/2 a, w += dt/2 alpha.
  * ---------------------------------------------------------------------------------- */
 int or_step(const or_params *p, int64_t n, double *x, double *v, double *w,
@@ -678,6 +851,14 @@ int or_step(const or_params *p, int64_t n, double *x, double *v, double *w,
                 v[i] = -Omega * yr; v[n + i] = Omega * xr; v[2 * n + i] = 0.0;
                 w[i] = 0.0; w[n + i] = 0.0; w[2 * n + i] = Omega;
             }
+        }
+        if (p->coll_alpha > 0.0) {
+            double *vn = (double *)malloc((size_t)3 * (n > 0 ? n : 1) * sizeof(double));
+            if (!vn) return OR_E_INVALID;
+            st = or_collide(p, n, x, v, species, kind, brute, vn);
+            if (!st) memcpy(v, vn, (size_t)3 * n * sizeof(double));
+            free(vn);
+            if (st) return st;
         }
         st = or_evaluate(p, n, x, v, w, species, kind, brute, rho, P, S, acc, alpha);
         if (st) return st;
