@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2405_03980_amd", "tuned.json"))
+    ap.add_argument("--f1-steps", type=int, default=20,
+                    help="timed steps with the pressure filter and the collision step on (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=20,
                     help="steps of the batched 64-instance ensemble (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
@@ -214,9 +216,9 @@ def main():
     n, nf = w.n, w.n_fluid
     print(f"[bench] {name}: {n} particles ({nf} fluid)", file=sys.stderr, flush=True)
 
-    def run(precision, steps, warmup, tuning, vortex=False):
+    def run(precision, steps, warmup, tuning, vortex=False, extra=None):
         tun, cf = tuning
-        s = S.Simulation(dict(w.params, cell_factor=cf), w.n, precision=precision)
+        s = S.Simulation(dict(w.params, cell_factor=cf, **(extra or {})), w.n, precision=precision)
         if tun:
             s.set_tuning(**tun)
         s.init(w.x, w.v, w.omega, w.species, w.kind)
@@ -253,7 +255,7 @@ def main():
     assert nsteps == args.steps
     ms_step = 1e3 * elapsed / args.steps
     value = n * args.steps / elapsed
-    per = {k: v / nsteps for k, v in ms.items()}
+    per = {k: v / nsteps for k, v in ms.items() if k not in ("collide", "filter")}
     print(f"[bench] mixed: {ms_step:.3f} ms/step; per kernel (ms): "
           + ", ".join(f"{k}={v:.3f}" for k, v in per.items()), file=sys.stderr, flush=True)
 
@@ -293,6 +295,17 @@ def main():
                 "after_steps": args.warmup + args.steps}
         print(f"[bench] fp64: {fp64['ms_per_step']} ms/step; mixed vs fp64 "
               f"{fp64['mixed_error_vs_fp64']}", file=sys.stderr, flush=True)
+    f1 = None
+    if args.f1_steps > 0:
+        # the same workload with Algorithm 1's pressure filter and collision step switched
+        # on (the lattice keeps every pair beyond the collision distance, so the collision
+        # step costs its search only)
+        f1p = dict(pressure_filter=1, coll_alpha=0.8, coll_e=0.3)
+        e1, ms1, n1, _ = run(L.FP32_MIXED, args.f1_steps, args.warmup, tuning, extra=f1p)
+        f1 = dict(f1p, steps=args.f1_steps, ms_per_step=round(1e3 * e1 / args.f1_steps, 3),
+                  value=n * args.f1_steps / e1,
+                  kernel_ms={k: round(v / n1, 4) for k, v in ms1.items()})
+        print(f"[bench] with filter and collisions: {f1}", file=sys.stderr, flush=True)
     batch = batch_bench(args.batch_steps, args.tuning) if args.batch_steps > 0 else None
     if batch:
         print(f"[bench] batch: {batch}", file=sys.stderr, flush=True)
@@ -312,6 +325,7 @@ def main():
         "fp64_gpu": fp64,
         "batch64": batch,
         "vortex_diag": vortex,
+        "filter_collide": f1,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define SPH_ABI_VERSION 1u
+#define SPH_ABI_VERSION 2u
 
 typedef enum {
     SPH_OK = 0,
@@ -94,7 +94,22 @@ typedef struct {
     double C_l;             /* local-interaction (mutual friction) coefficient            */
     double kappa_I;         /* spin inertia I = kappa_I m dx^2                            */
     int32_t cell_factor;    /* cells per interaction radius along each axis (1..4)        */
-    int32_t reserved;       /* must be 0                                                  */
+    int32_t pressure_filter;/* 1: pressure filter of Algorithm 1 after the EOS; 0: none.   */
+                            /* Reading (the paper cites the filter without its formula):   */
+                            /* P_i <- (V_i P_i W(0) + sum_j V_j P_j W_ij)                  */
+                            /*       / (V_i W(0) + sum_j V_j W_ij), V = m/rho, over fluid   */
+                            /* and inner-wall particles and neighbours; outer walls keep   */
+                            /* P = 0 and are not sources.  The forces and the P returned   */
+                            /* by sph_read_fields use the filtered pressure.               */
+    double coll_alpha;      /* collision step of Algorithm 1: distance coll_alpha * dx,    */
+                            /* 0 <= coll_alpha * dx < 2h; 0 switches it off.  Reading (the */
+                            /* paper cites the model without its formula): after each      */
+                            /* drift, every fluid particle i closer than that to a         */
+                            /* neighbour j it approaches ((v_i - v_j).(x_i - x_j) < 0)     */
+                            /* takes v_i -= (1 + coll_e) mu ((v_ij . r_ij) / r^2) r_ij,    */
+                            /* mu = m_j / (m_i + m_j) (1 for a wall neighbour), all pairs  */
+                            /* from the velocities before the step; walls are unchanged    */
+    double coll_e;          /* restitution of the collision step, in [0, 1]               */
 } sph_params;
 
 /* Launch shape of the kernels (performance only; results do not depend on it).
@@ -117,7 +132,8 @@ typedef struct sph_sim sph_sim;      /* one SPH instance (opaque, host memory)  
 typedef struct sph_batch sph_batch;  /* an ensemble of independent instances              */
 
 /* Defaults: abi_version, Wendland C2, FP32_MIXED, periodic unit box, rho0 = 1, gamma = 7,
- * default masses, kappa_I = 0.4, cell_factor = 1; dx, h, c0 must still be set. */
+ * default masses, kappa_I = 0.4, cell_factor = 1, no pressure filter, no collision step;
+ * dx, h, c0 must still be set. */
 sph_status sph_params_init(sph_params *p);
 
 /* Cells per axis of the search grid for these parameters (host only).
@@ -145,9 +161,10 @@ sph_status sph_init_particles(sph_sim *s, const double *x, const double *v,
 
 /* Advance nsteps >= 0 velocity-Verlet steps of size dt > 0 with walls turning at Omega
  * (rad per unit time, about the z axis through x = y = 0; ignored when there are no wall
- * particles).  Per step: half kick and drift (walls rotated exactly), cell list, density
- * and EOS, pair forces and torques, closing half kick (Algorithm 1).  The closing half
- * kick is folded into the next step's opening kick; reads apply it. */
+ * particles).  Per step: half kick and drift (walls rotated exactly), cell list, the
+ * collision step (if enabled), density and EOS, the pressure filter (if enabled), pair
+ * forces and torques, closing half kick (Algorithm 1).  The closing half kick is folded
+ * into the next step's opening kick; reads apply it. */
 sph_status sph_step(sph_sim *s, double dt, double Omega, int32_t nsteps);
 
 /* Write the current fields by id; any pointer may be NULL to skip it.
@@ -210,7 +227,9 @@ typedef enum {
     SPH_K_REORDER = 3,  /* in-cell ordering and state move                                */
     SPH_K_DENSITY = 4,  /* density, EOS                                                   */
     SPH_K_FORCE = 5,    /* pair forces and torques                                        */
-    SPH_K_COUNT = 6
+    SPH_K_COLLIDE = 6,  /* collision step (when enabled)                                   */
+    SPH_K_FILTER = 7,   /* pressure filter (when enabled)                                  */
+    SPH_K_COUNT = 8
 } sph_kernel_group;
 sph_status sph_profile_begin(sph_sim *s);
 sph_status sph_profile_end(sph_sim *s, double ms[SPH_K_COUNT], int32_t *nsteps);

@@ -11,7 +11,7 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libsph4he.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 OK, E_INVALID, E_WORKSPACE, E_HIP, E_STATE, E_DOMAIN, E_NONFINITE, E_UNSUPPORTED, E_CAPACITY = range(9)
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_WORKSPACE", 3: "E_HIP", 4: "E_STATE",
@@ -32,7 +32,8 @@ class SphParams(C.Structure):
         ("mass", C.c_double * 2),
         ("eta", C.c_double), ("sigma_T", C.c_double), ("C_l", C.c_double),
         ("kappa_I", C.c_double),
-        ("cell_factor", C.c_int32), ("reserved", C.c_int32),
+        ("cell_factor", C.c_int32), ("pressure_filter", C.c_int32),
+        ("coll_alpha", C.c_double), ("coll_e", C.c_double),
     ]
 
 
@@ -79,7 +80,7 @@ _PROTOS = {
     "sph_batch_profile_end": (C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
 }
 
-KERNEL_GROUPS = ("keys", "scan", "scatter", "reorder", "density", "force")
+KERNEL_GROUPS = ("keys", "scan", "scatter", "reorder", "density", "force", "collide", "filter")
 
 _lib = None
 
@@ -122,6 +123,8 @@ def make_params(d: dict, precision: int | None = None) -> SphParams:
     p.eta, p.sigma_T, p.C_l = float(d["eta"]), float(d["sigma_T"]), float(d["C_l"])
     p.kappa_I = float(d["kappa_I"])
     p.cell_factor = int(d.get("cell_factor", 1))
+    p.pressure_filter = int(d.get("pressure_filter", 0))
+    p.coll_alpha, p.coll_e = float(d.get("coll_alpha", 0.0)), float(d.get("coll_e", 0.0))
     return p
 
 

@@ -637,6 +637,163 @@ __global__ void k_force(DevState s)
     if (err) atomicOr(s.err, err);
 }
 
+// Pressure filter of particle p (Algorithm 1, after the EOS): the volume-weighted Shepard
+// average of the pressure over p and its fluid and inner-wall neighbours,
+//   P~ = (V_p P_p W(0) + sum V_q P_q W_pq) / (V_p W(0) + sum V_q W_pq).
+// Outer walls are not averaged and are not sources.  Reads V (aux) and P (rhoP), writes
+// P~ to pf and P~/rho^2 to aux, which the filter itself does not read.
+template <typename R, bool KAHAN>
+__device__ __forceinline__ uint32_t filter_one(const DevState &s, const InstDesc *d, uint32_t p)
+{
+    const uint32_t N = s.N;
+    const int cur = s.cur;
+    const uint8_t *SK = s.sk[cur];
+    R *AUX = (R *)s.aux;
+    const R *RP = (const R *)s.rhoP;
+    R *PF = (R *)s.pf;
+    if ((SK[p] >> 1) == KIND_WALL_OUTER) {
+        PF[p] = RP[2 * (size_t)p + 1];
+        return 0u;
+    }
+    const double *X = s.x[cur];
+    const double xi0 = X[p], xi1 = X[N + p], xi2 = X[2 * N + p];
+    const uint32_t cxyz = s.cell_xyz[s.pcell[p]];
+    const int kernel = d->kernel;
+    const double cut2 = d->cut2;
+    const R inv_h = (R)d->inv_h, wnorm = (R)d->wnorm;
+    uint32_t err = 0;
+    Acc<R, KAHAN> num, den;
+    for_each_cell(s, d, cxyz & 1023, (cxyz >> 10) & 1023, cxyz >> 20, err,
+                  [&](uint32_t b, uint32_t e) {
+        for (uint32_t q = b; q < e; ++q) {
+            const double xq0 = X[q], xq1 = X[N + q], xq2 = X[2 * N + q];
+            double r2 = r2_exact(min_img(d, 0, xi0 - xq0), min_img(d, 1, xi1 - xq1),
+                                 min_img(d, 2, xi2 - xq2));
+            if (!(r2 < cut2) || q == p || (SK[q] >> 1) == KIND_WALL_OUTER) continue;
+            const R W = kernel_W<R>(kernel, (R)r2, inv_h, wnorm);
+            const R Vq = AUX[4 * (size_t)q];
+            num.add(Vq * RP[2 * (size_t)q + 1] * W);
+            den.add(Vq * W);
+        }
+    });
+    const double Vp = (double)AUX[4 * (size_t)p], Pp = (double)RP[2 * (size_t)p + 1];
+    const double Pt = (Vp * Pp * d->W0 + num.value()) / (Vp * d->W0 + den.value());
+    PF[p] = (R)Pt;
+    AUX[4 * (size_t)p + 1] = (R)(Pt * (double)AUX[4 * (size_t)p + 2]);
+    return err | (isfinite(Pt) ? 0u : (uint32_t)ERR_NONFINITE);
+}
+
+template <typename R, bool KAHAN>
+__global__ void k_filter(DevState s)
+{
+    PIdx t = map_thread(s);
+    if (!t.active || !t.d->pfilter) return;
+    uint32_t err = filter_one<R, KAHAN>(s, t.d, t.p);
+    if (err) atomicOr(s.err, err);
+}
+
+// Collision step (Algorithm 1), FP64 on both paths, one thread per fluid particle of the
+// instances that have it on.  A fluid particle i closer than rc to a neighbour j that it
+// approaches ((v_i - v_j).(x_i - x_j) < 0) takes
+//   dv_i = -(1 + e) mu (v_ij . r_ij) / |r_ij|^2 r_ij,  mu = m_j / (m_i + m_j), 1 for walls,
+// summed over all such neighbours from the velocities before the step; the new velocities
+// go to the other velocity buffer (free between the reorder and the next step's) and
+// k_collide_apply copies them back.  Only cells within rc of the particle are walked
+// (rc < 2h; the test on each axis keeps a margin, so pruning never drops a pair).
+__global__ void k_collide(DevState s)
+{
+    PIdx t = map_thread(s);
+    if (!t.active) return;
+    const InstDesc *d = t.d;
+    if (!d->coll) return;
+    const uint32_t N = s.N, p = t.p;
+    const int cur = s.cur;
+    const uint8_t *SK = s.sk[cur];
+    const uint8_t ski = SK[p];
+    if ((ski >> 1) != KIND_FLUID) return;
+    const double *X = s.x[cur], *Vv = s.v[cur];
+    double *VN = s.v[cur ^ 1];
+    const double xi[3] = {X[p], X[N + p], X[2 * N + p]};
+    const double vi[3] = {Vv[p], Vv[N + p], Vv[2 * N + p]};
+    const uint32_t cxyz = s.cell_xyz[s.pcell[p]];
+    const int c[3] = {(int)(cxyz & 1023), (int)((cxyz >> 10) & 1023), (int)(cxyz >> 20)};
+    // cell offsets on each axis whose slab lies within rc of the particle
+    int olo[3], ohi[3];
+    for (int a = 0; a < 3; a++) {
+        const double e = d->edge[a], reach = d->coll_rc + 1e-6 * e;
+        const double below = xi[a] - (d->lo[a] + (double)c[a] * e);  // to the cell's lower face
+        const double above = e - below;                                // to its upper face
+        olo[a] = 0;
+        ohi[a] = 0;
+        for (int o = 1; o <= d->cf; o++) {
+            if (below + (double)(o - 1) * e < reach) olo[a] = -o;
+            if (above + (double)(o - 1) * e < reach) ohi[a] = o;
+        }
+    }
+    const double mi = d->mass[ski & 1];
+    const double rc2 = d->coll_rc2, e1 = d->coll_e1;
+    const int n0 = d->n[0], n1 = d->n[1], n2 = d->n[2];
+    uint32_t err = 0;
+    double dv[3] = {0.0, 0.0, 0.0};
+    for (int oz = olo[2]; oz <= ohi[2]; ++oz) {
+        int z = c[2] + oz;
+        if (d->periodic[2]) { z += z < 0 ? n2 : 0; z -= z >= n2 ? n2 : 0; }
+        else if (z < 0 || z >= n2) continue;
+        for (int oy = olo[1]; oy <= ohi[1]; ++oy) {
+            int y = c[1] + oy;
+            if (d->periodic[1]) { y += y < 0 ? n1 : 0; y -= y >= n1 ? n1 : 0; }
+            else if (y < 0 || y >= n1) continue;
+            for (int ox = olo[0]; ox <= ohi[0]; ++ox) {
+                int x = c[0] + ox;
+                if (d->periodic[0]) { x += x < 0 ? n0 : 0; x -= x >= n0 ? n0 : 0; }
+                else if (x < 0 || x >= n0) continue;
+                const uint32_t lin = (uint32_t)x + (uint32_t)n0 * ((uint32_t)y + (uint32_t)n1 * (uint32_t)z);
+                const uint32_t r = s.rank_of_lin[d->cell_off + lin];
+                const uint32_t b = s.start[r], e = s.start[r + 1];
+                if (e - b > (uint32_t)kMaxCell) { err |= ERR_CAPACITY; continue; }
+                for (uint32_t q = b; q < e; ++q) {
+                    if (q == p) continue;
+                    const double r0 = min_img(d, 0, xi[0] - X[q]);
+                    const double r1 = min_img(d, 1, xi[1] - X[N + q]);
+                    const double rr2 = min_img(d, 2, xi[2] - X[2 * N + q]);
+                    const double d2 = r2_exact(r0, r1, rr2);
+                    if (!(d2 < rc2)) continue;
+                    double vn;
+                    {
+#pragma clang fp contract(off)
+                        vn = (vi[0] - Vv[q]) * r0;
+                        vn = vn + (vi[1] - Vv[N + q]) * r1;
+                        vn = vn + (vi[2] - Vv[2 * N + q]) * rr2;
+                    }
+                    if (!(vn < 0.0)) continue;
+                    const uint8_t skq = SK[q];
+                    const double mu = (skq >> 1) == KIND_FLUID ? d->mass[skq & 1] / (mi + d->mass[skq & 1]) : 1.0;
+                    const double g = -e1 * mu * vn / d2;
+                    dv[0] += g * r0;
+                    dv[1] += g * r1;
+                    dv[2] += g * rr2;
+                }
+            }
+        }
+    }
+    for (int a = 0; a < 3; a++) {
+        const double vnew = vi[a] + dv[a];
+        VN[(size_t)a * N + p] = vnew;
+        if (!isfinite(vnew)) err |= ERR_NONFINITE;
+    }
+    if (err) atomicOr(s.err, err);
+}
+
+__global__ void k_collide_apply(DevState s)
+{
+    PIdx t = map_thread(s);
+    if (!t.active || !t.d->coll) return;
+    const uint32_t N = s.N, p = t.p;
+    const int cur = s.cur;
+    if ((s.sk[cur][p] >> 1) != KIND_FLUID) return;
+    for (int a = 0; a < 3; a++) s.v[cur][(size_t)a * N + p] = s.v[cur ^ 1][(size_t)a * N + p];
+}
+
 // ------------------------------------------------------------ brick sweeps ----------
 //
 // One workgroup per brick of 2x2x2 cells (edge >= 2h each).  The 4x4x4 cells around the
@@ -1118,6 +1275,59 @@ __device__ __forceinline__ void hit_share(Word &&word, uint32_t H, int g, int G,
 }
 
 
+// A lane's share of one target's hits, replayed from the mask words the density sweep
+// stored: share g of G takes hits [H g / G, H (g + 1) / G) of the H hits, in list order.
+// All of the target's words are loaded at once (no chain of dependent loads); next()
+// walks the share's hits in order.
+struct HitReplay {
+    const uint64_t *gm;
+    int NW, c;
+    uint32_t cnt;
+    uint64_t mc, nxt;  // bits of window c still to walk; window c + 1
+
+    __device__ __forceinline__ HitReplay(const uint64_t *gm_, int NW_, bool target, int g, int G)
+        : gm(gm_), NW(NW_), c(0), mc(0), nxt(0)
+    {
+        uint64_t mw[kCandWin];
+        uint32_t H = 0;
+#pragma unroll
+        for (int cc = 0; cc < kCandWin; cc++) {
+            mw[cc] = (target && cc < NW) ? gm[cc] : 0ull;
+            H += (uint32_t)__popcll(mw[cc]);
+        }
+        const uint32_t lo = (H * (uint32_t)g) / (uint32_t)G;
+        cnt = (H * (uint32_t)(g + 1)) / (uint32_t)G - lo;
+        uint32_t pre = 0, before = 0;
+#pragma unroll
+        for (int cc = 0; cc < kCandWin; cc++) {
+            pre += (uint32_t)__popcll(mw[cc]);
+            if (pre <= lo) {
+                c = cc + 1;
+                before = pre;
+            }
+        }
+#pragma unroll
+        for (int cc = 0; cc < kCandWin; cc++) {
+            if (cc == c) mc = mw[cc];
+            if (cc == c + 1) nxt = mw[cc];
+        }
+        if (cnt) mc = drop_low_bits(mc, lo - before);
+    }
+
+    // Staged index of the next hit, from the wave's list table.
+    __device__ __forceinline__ uint32_t next(const int16_t (*tbl)[64])
+    {
+        while (mc == 0) {
+            mc = nxt;
+            ++c;
+            nxt = c + 1 < NW ? gm[c + 1] : 0ull;
+        }
+        const int j = __builtin_ctzll(mc);
+        mc &= mc - 1;
+        return (uint32_t)tbl[c][j];
+    }
+};
+
 // Ballot tests of targets kbase .. kbase + ntc - 1 (staged indices) against the first NWc
 // candidate windows, NWc fixed at compile time so that the windows need no branch per
 // target.  The ballots of one target stay in scalar registers until lane t copies them
@@ -1357,50 +1567,13 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
             const uint32_t ki = toff + t0 + t;
             const float4 Ai = SA[ki], Bi = SB[ki], Ci = SC[ki];
             const PairI I = pair_target(K, Ai, Bi, Ci);
-            // all of the target's mask words at once (no chain of dependent loads); group g
-            // takes hits [lo, lo + cnt) in list order, starting in window c
-            const uint64_t *gm = s.masks + (size_t)p * kMaskSlots;
-            uint64_t mw[kCandWin];
-            uint32_t H = 0;
-#pragma unroll
-            for (int cc = 0; cc < kCandWin; cc++) {
-                mw[cc] = (target && cc < NW) ? gm[cc] : 0ull;
-                H += (uint32_t)__popcll(mw[cc]);
-            }
-            const uint32_t lo = (H * (uint32_t)g) / (uint32_t)G;
-            const uint32_t cnt = (H * (uint32_t)(g + 1)) / (uint32_t)G - lo;
-            int c = 0;
-            uint32_t pre = 0, before = 0;
-#pragma unroll
-            for (int cc = 0; cc < kCandWin; cc++) {
-                pre += (uint32_t)__popcll(mw[cc]);
-                if (pre <= lo) {
-                    c = cc + 1;
-                    before = pre;
-                }
-            }
-            uint64_t mc = 0, nxt = 0;  // bits of window c still to walk; window c + 1
-#pragma unroll
-            for (int cc = 0; cc < kCandWin; cc++) {
-                if (cc == c) mc = mw[cc];
-                if (cc == c + 1) nxt = mw[cc];
-            }
-            if (cnt) mc = drop_low_bits(mc, lo - before);
+            HitReplay hr(s.masks + (size_t)p * kMaskSlots, NW, target, g, G);
+            const uint32_t cnt = hr.cnt;
             Acc<float, KAHAN> F0, F1, F2, T0, T1, T2;
-            auto next_k = [&]() {
-                while (mc == 0) {
-                    mc = nxt;
-                    ++c;
-                    nxt = c + 1 < NW ? gm[c + 1] : 0ull;
-                }
-                const int j = __builtin_ctzll(mc);
-                mc &= mc - 1;
-                return (uint32_t)tbl[w][c][j];
-            };
             // per-lane trip count, two hits per trip (as in the density sweep)
 #pragma unroll 2
             for (uint32_t i = 0; i < cnt; i++) {
-                const uint32_t k = next_k();
+                const uint32_t k = hr.next(tbl[w]);
                 const float4 A = SA[k], B = SB[k], C = SC[k];
                 float f[3], nn[3];
                 pair_force_f32<KT, EQM>(K, I, A, B, C, Ai.x - A.x, Ai.y - A.y, Ai.z - A.z,
@@ -1434,6 +1607,145 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
         if (eq) sweep(Cub(), Eq());
         else sweep(Cub(), Uneq());
     }
+    if (err) atomicOr(s.err, err);
+}
+
+// Stages what the pressure filter reads of the brick's M neighbourhood particles: the
+// position relative to the brick centre in units of h with the source volume V (0 for an
+// outer wall, which is not a source), and V P.  Spread over the threads as in
+// stage_force.
+__device__ __forceinline__ void stage_filter(const DevState &s, const BrickFrame &F, uint32_t M,
+                                             double ih, float4 *SA, float *SP)
+{
+    const uint32_t N = s.N;
+    const int cur = s.cur;
+    const double *X = s.x[cur];
+    const uint8_t *SK = s.sk[cur];
+    const float *AUX = (const float *)s.aux;
+    const float *RP = (const float *)s.rhoP;
+    for (uint32_t k0 = threadIdx.x; k0 < M; k0 += 3 * kBrickThreads) {
+        uint32_t kk[3], qq[3];
+        int sl[3];
+        for (int u = 0; u < 3; u++) {
+            kk[u] = k0 + (uint32_t)u * kBrickThreads;
+            sl[u] = slot_of(F, min(kk[u], M - 1));
+            qq[u] = F.begin[sl[u]] + (min(kk[u], M - 1) - F.off[sl[u]]);
+        }
+        double px[3][3];
+        float vq[3], pq[3];
+        uint8_t sk[3];
+        for (int u = 0; u < 3; u++) {
+            const uint32_t q = qq[u];
+            for (int a = 0; a < 3; a++) px[u][a] = X[(size_t)a * N + q];
+            vq[u] = AUX[4 * (size_t)q];
+            pq[u] = RP[2 * (size_t)q + 1];
+            sk[u] = SK[q];
+        }
+        for (int u = 0; u < 3; u++) {
+            if (kk[u] >= M) break;
+            const uint32_t k = kk[u];
+            const float Vs = (sk[u] >> 1) == KIND_WALL_OUTER ? 0.0f : vq[u];
+            SA[k] = make_float4((float)(((px[u][0] + F.shift[sl[u]][0]) - F.origin[0]) * ih),
+                                (float)(((px[u][1] + F.shift[sl[u]][1]) - F.origin[1]) * ih),
+                                (float)(((px[u][2] + F.shift[sl[u]][2]) - F.origin[2]) * ih), Vs);
+            SP[k] = Vs * pq[u];
+        }
+    }
+}
+
+// Pressure filter over the brick sweeps' neighbour masks (the density sweep's, replayed as
+// in the force sweep): lanes = (target, group g of G) over the block's fluid and
+// inner-wall targets; outer walls copy their fixed pressure directly.  The kernel shape
+// sums are scaled by the normalisation in FP64, where the self term joins them; the
+// stage capacity is the force sweep's, so a brick the density sweep could not stage (and
+// left without masks) is filtered per particle here too.
+template <bool KAHAN>
+__global__ void __launch_bounds__(kBrickThreads, 4) k_filter_cand(DevState s)
+{
+    __shared__ BrickFrame F;
+    __shared__ float4 SA[kStageForce];  // position (brick frame), source volume
+    __shared__ float SP[kStageForce];   // source volume times pressure
+    __shared__ int16_t tbl[kBrickThreads / 64][kCandWin][64];
+    const uint32_t brick = brick_of_workgroup(blockIdx.x, gridDim.x);
+    const uint32_t bxyz = s.brick_xyz[brick];
+    const InstDesc *d = s.desc + s.brick_inst[brick];
+    if (!d->pfilter) return;  // the same for the whole workgroup
+    const uint8_t *SK = s.sk[s.cur];
+    float *AUX = (float *)s.aux;
+    const float *RP = (const float *)s.rhoP;
+    float *PF = (float *)s.pf;
+    const uint32_t M = brick_frame(s, d, brick, bxyz, F, kStageForce);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int ts[3];
+    const bool has_cell = brick_target(d, bxyz, w, ts);
+    const int tslot = slot_index(ts[0], ts[1], ts[2]);
+    uint32_t err = 0;
+    if (!F.ok) {
+        if (has_cell) {
+            const uint32_t nt = F.off[tslot + 1] - F.off[tslot];
+            for (uint32_t i = lane; i < nt; i += 64) err |= filter_one<float, KAHAN>(s, d, F.begin[tslot] + i);
+        }
+        if (err) atomicOr(s.err, err);
+        return;
+    }
+    stage_filter(s, F, M, d->inv_h, SA, SP);
+    __syncthreads();
+    if (!has_cell) return;
+    const uint32_t toff = F.off[tslot], pbase = F.begin[tslot];
+    const uint32_t nt = F.off[tslot + 1] - toff;
+    if (nt == 0) return;
+    const StencilList S = stencil_list(F, ts, lane, &tbl[w][0][0]);
+    if (S.NW > (uint32_t)kCandWin) {
+        for (uint32_t i = lane; i < nt; i += 64) err |= filter_one<float, KAHAN>(s, d, pbase + i);
+        if (err) atomicOr(s.err, err);
+        return;
+    }
+    const int NW = (int)S.NW;
+    const double wn = d->wnorm, W0 = d->W0;
+    auto sweep = [&](auto kt) {
+        constexpr int KT = decltype(kt)::value;
+        for (uint32_t t0 = 0; t0 < nt; t0 += 64) {
+            const uint32_t nb = min(64u, nt - t0);
+            uint32_t sk_t = 0;
+            if ((uint32_t)lane < nb) sk_t = SK[pbase + t0 + lane];
+            const bool tgt = (uint32_t)lane < nb && (sk_t >> 1) != KIND_WALL_OUTER;
+            const uint64_t Mt = __ballot(tgt);
+            if ((uint32_t)lane < nb && !tgt) {
+                const uint32_t q = pbase + t0 + lane;
+                PF[q] = RP[2 * (size_t)q + 1];
+            }
+            if (Mt == 0) continue;
+            const int n = __popcll(Mt);
+            const int G = 64 / n;
+            const int g = lane / n;
+            const bool target = g < G;
+            const uint32_t t = (uint32_t)__builtin_ctzll(drop_low_bits(Mt, (uint32_t)(lane % n)));
+            const uint32_t p = pbase + t0 + t;
+            const float4 Ai = SA[toff + t0 + t];
+            HitReplay hr(s.masks + (size_t)p * kMaskSlots, NW, target, g, G);
+            Acc<float, KAHAN> num, den;
+#pragma unroll 2
+            for (uint32_t i = 0; i < hr.cnt; i++) {
+                const uint32_t k = hr.next(tbl[w]);
+                const float4 A = SA[k];
+                const float d0 = Ai.x - A.x, d1 = Ai.y - A.y, d2 = Ai.z - A.z;
+                const float W = shape_W<KT>(d0 * d0 + d1 * d1 + d2 * d2);
+                num.add(SP[k] * W);
+                den.add(A.w * W);
+            }
+            const double sn = group_total(num.s, KAHAN ? num.c : 0.0f, lane, n, G);
+            const double sd = group_total(den.s, KAHAN ? den.c : 0.0f, lane, n, G);
+            if (target && g == 0) {
+                const double Vp = (double)AUX[4 * (size_t)p], Pp = (double)RP[2 * (size_t)p + 1];
+                const double Pt = (Vp * Pp * W0 + wn * sn) / (Vp * W0 + wn * sd);
+                PF[p] = (float)Pt;
+                AUX[4 * (size_t)p + 1] = (float)(Pt * (double)AUX[4 * (size_t)p + 2]);
+                if (!isfinite(Pt)) err |= ERR_NONFINITE;
+            }
+        }
+    };
+    if (d->kernel == KERNEL_WENDLAND) sweep(std::integral_constant<int, KERNEL_WENDLAND>());
+    else sweep(std::integral_constant<int, KERNEL_CUBIC>());
     if (err) atomicOr(s.err, err);
 }
 
@@ -1482,7 +1794,7 @@ __global__ void k_read(DevState s, double pend, double *x, double *v, double *w,
     }
     const R *rp = (const R *)s.rhoP + 2 * (size_t)p;
     if (rho) rho[id] = (double)rp[0];
-    if (P) P[id] = (double)rp[1];
+    if (P) P[id] = (double)(t.d->pfilter ? ((const R *)s.pf)[p] : rp[1]);
 }
 
 __global__ void k_debug_keys(DevState s, uint32_t *key_by_id, uint32_t *perm)
@@ -1833,6 +2145,25 @@ hipError_t launch_force(const DevState &d, const Launch &L, hipStream_t st)
     if (d.precision == 0) k_force<double, false><<<g, L.bs_force, 0, st>>>(d);
     else if (L.sweep == SWEEP_CAND && d.n_bricks) k_force_cand<true><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
     else k_force<float, true><<<g, L.bs_force, 0, st>>>(d);
+    return hipGetLastError();
+}
+
+hipError_t launch_filter(const DevState &d, const Launch &L, hipStream_t st)
+{
+    if (!d.any_filter) return hipSuccess;
+    unsigned g = grid_for(d.n_waves, L.bs_density);
+    if (d.precision == 0) k_filter<double, false><<<g, L.bs_density, 0, st>>>(d);
+    else if (L.sweep == SWEEP_CAND && d.n_bricks) k_filter_cand<true><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
+    else k_filter<float, true><<<g, L.bs_density, 0, st>>>(d);
+    return hipGetLastError();
+}
+
+hipError_t launch_collide(const DevState &d, const Launch &L, hipStream_t st)
+{
+    if (!d.any_coll) return hipSuccess;
+    unsigned g = grid_for(d.n_waves, L.bs_stream);
+    k_collide<<<g, L.bs_stream, 0, st>>>(d);
+    k_collide_apply<<<g, L.bs_stream, 0, st>>>(d);
     return hipGetLastError();
 }
 

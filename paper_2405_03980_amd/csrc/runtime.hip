@@ -122,7 +122,12 @@ sph_status validate(const sph_params *p, std::string &msg)
     if (!isfinite(p->sigma_T) || !isfinite(p->C_l)) { msg = "sigma_T and C_l must be finite"; return SPH_E_INVALID; }
     if (!(p->kappa_I > 0.0) || !isfinite(p->kappa_I)) { msg = "kappa_I must be positive"; return SPH_E_INVALID; }
     if (p->cell_factor < 1 || p->cell_factor > 4) { msg = "cell_factor must be in 1..4"; return SPH_E_INVALID; }
-    if (p->reserved != 0) { msg = "reserved must be 0"; return SPH_E_INVALID; }
+    if (p->pressure_filter != 0 && p->pressure_filter != 1) { msg = "pressure_filter must be 0 or 1"; return SPH_E_INVALID; }
+    if (!(p->coll_alpha >= 0.0) || !isfinite(p->coll_alpha) || !(p->coll_alpha * p->dx < 2.0 * p->h)) {
+        msg = "coll_alpha must satisfy 0 <= coll_alpha dx < 2h";
+        return SPH_E_INVALID;
+    }
+    if (!(p->coll_e >= 0.0 && p->coll_e <= 1.0)) { msg = "coll_e must be in [0, 1]"; return SPH_E_INVALID; }
     for (int a = 0; a < 3; a++)
         if (!isfinite(p->lo[a]) || !isfinite(p->hi[a])) { msg = "lo/hi must be finite"; return SPH_E_INVALID; }
     int32_t n[3];
@@ -145,7 +150,8 @@ struct Carver {
     }
 };
 
-void carve(Carver &c, DevState &d, int n_inst, uint32_t N, uint32_t C, uint32_t NB, int precision)
+void carve(Carver &c, DevState &d, int n_inst, uint32_t N, uint32_t C, uint32_t NB, int precision,
+           bool filter)
 {
     size_t rs = precision == SPH_FP64 ? sizeof(double) : sizeof(float);
     size_t n3 = 3 * (size_t)N;
@@ -162,6 +168,7 @@ void carve(Carver &c, DevState &d, int n_inst, uint32_t N, uint32_t C, uint32_t 
     d.alpha = c.take<char>(n3 * rs);
     d.aux = c.take<char>(4 * (size_t)N * rs);
     d.rhoP = c.take<char>(2 * (size_t)N * rs);
+    d.pf = c.take<char>((filter ? (size_t)N : 1) * rs);
     d.key = c.take<uint32_t>(N);
     d.slot = c.take<uint32_t>(N);
     d.tmp = c.take<uint32_t>(N);
@@ -186,6 +193,7 @@ struct Plan {
     std::vector<InstDesc> desc;
     uint32_t N = 0, C = 0, n_waves = 0;
     uint32_t n_bricks = 0;  // 0 unless every instance has cell_factor 1
+    bool any_filter = false, any_coll = false;
 };
 
 sph_status plan(int32_t n_inst, const sph_params *params, const int64_t *counts, Plan &pl,
@@ -232,6 +240,13 @@ sph_status plan(int32_t n_inst, const sph_params *params, const int64_t *counts,
         d.eta = p->eta;
         d.sigma_T = p->sigma_T;
         d.C_l = p->C_l;
+        d.coll_rc = p->coll_alpha * p->dx;
+        d.coll_rc2 = d.coll_rc * d.coll_rc;
+        d.coll_e1 = 1.0 + p->coll_e;
+        d.pfilter = p->pressure_filter;
+        d.coll = p->coll_alpha > 0.0 ? 1 : 0;
+        pl.any_filter = pl.any_filter || d.pfilter;
+        pl.any_coll = pl.any_coll || d.coll;
         d.cf = p->cell_factor;
         d.kernel = p->kernel;
         uint64_t nc = (uint64_t)n[0] * n[1] * n[2];
@@ -390,7 +405,9 @@ sph_status prof_mark(sph_batch *b, int tag)
     return SPH_OK;
 }
 
-// One velocity Verlet step: opening kick + drift, cell list, density, forces.
+// One velocity Verlet step: opening kick + drift, cell list, collision step, density,
+// pressure filter, forces (the collision step and the filter for instances that have
+// them on; mode 0, the evaluation at load, has no collision step).
 sph_status enqueue_step(sph_batch *b, int mode, double kick, double dt)
 {
     DevState &d = b->ds;
@@ -405,8 +422,16 @@ sph_status enqueue_step(sph_batch *b, int mode, double kick, double dt)
     if ((s = prof_mark(b, SPH_K_REORDER)) != SPH_OK) return s;
     if ((s = check_launch(b, launch_reorder(d, b->L, st, mode, kick, dt), "reorder")) != SPH_OK) return s;
     d.cur ^= 1;
+    if (mode == 1 && d.any_coll) {
+        if ((s = prof_mark(b, SPH_K_COLLIDE)) != SPH_OK) return s;
+        if ((s = check_launch(b, launch_collide(d, b->L, st), "collide")) != SPH_OK) return s;
+    }
     if ((s = prof_mark(b, SPH_K_DENSITY)) != SPH_OK) return s;
     if ((s = check_launch(b, launch_density(d, b->L, st), "density")) != SPH_OK) return s;
+    if (d.any_filter) {
+        if ((s = prof_mark(b, SPH_K_FILTER)) != SPH_OK) return s;
+        if ((s = check_launch(b, launch_filter(d, b->L, st), "pressure filter")) != SPH_OK) return s;
+    }
     if ((s = prof_mark(b, SPH_K_FORCE)) != SPH_OK) return s;
     if ((s = check_launch(b, launch_force(d, b->L, st), "force")) != SPH_OK) return s;
     if ((s = prof_mark(b, -1)) != SPH_OK) return s;
@@ -591,7 +616,7 @@ sph_status sph_batch_workspace_bytes(int32_t n_inst, const sph_params *params,
     if (st != SPH_OK) return st;
     Carver c;
     DevState d{};
-    carve(c, d, n_inst, pl.N, pl.C, pl.n_bricks, params[0].precision);
+    carve(c, d, n_inst, pl.N, pl.C, pl.n_bricks, params[0].precision, pl.any_filter);
     *bytes = c.off;
     return SPH_OK;
 }
@@ -611,7 +636,7 @@ sph_status sph_batch_create(int32_t n_inst, const sph_params *params, const int6
     if (st != SPH_OK) return st;
     Carver c;
     DevState d{};
-    carve(c, d, n_inst, pl.N, pl.C, pl.n_bricks, params[0].precision);
+    carve(c, d, n_inst, pl.N, pl.C, pl.n_bricks, params[0].precision, pl.any_filter);
     if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || ws_bytes < c.off) return SPH_E_WORKSPACE;
     sph_batch *b = new (std::nothrow) sph_batch();
     if (!b) return SPH_E_INVALID;
@@ -622,13 +647,15 @@ sph_status sph_batch_create(int32_t n_inst, const sph_params *params, const int6
     b->steptab.assign(n_inst, StepParams{1.0, 0.0, 0.0, 0.0});
     Carver c2;
     c2.base = (char *)workspace;
-    carve(c2, b->ds, n_inst, pl.N, pl.C, pl.n_bricks, params[0].precision);
+    carve(c2, b->ds, n_inst, pl.N, pl.C, pl.n_bricks, params[0].precision, pl.any_filter);
     b->ds.precision = params[0].precision;
     b->ds.n_inst = n_inst;
     b->ds.cur = 0;
     b->ds.N = pl.N;
     b->ds.C = pl.C;
     b->ds.n_waves = pl.n_waves;
+    b->ds.any_filter = pl.any_filter ? 1 : 0;
+    b->ds.any_coll = pl.any_coll ? 1 : 0;
     std::vector<uint32_t> rank_of_lin, xyz, bxyz, binst;
     cell_tables(pl, rank_of_lin, xyz);
     brick_tables(pl, bxyz, binst);

@@ -30,6 +30,9 @@ struct InstDesc {
     double inv_mass[2], inv_inertia[2];
     double rho0, B;             // Tait: P = B ((rho/rho0)^7 - 1)
     double eta, sigma_T, C_l;
+    double coll_rc, coll_rc2;   // collision step: distance coll_alpha dx and its square
+    double coll_e1;             // 1 + restitution
+    int32_t pfilter, coll;      // pressure filter on; collision step on
     int32_t n[3], periodic[3];
     int32_t cf, kernel;
     uint32_t cell_off, n_cells; // this instance's cells in the global cell range
@@ -49,6 +52,8 @@ struct DevState {
     int n_inst;
     int cur;                // buffer (0/1) holding the current state
     uint32_t N, C, n_waves; // particles, cells, wavefronts over all instances
+    int any_filter;         // some instance has the pressure filter on
+    int any_coll;           // some instance has the collision step on
     InstDesc *desc;
     StepParams *steptab;
     double *x[2], *v[2], *w[2];   // [3][N] each
@@ -56,7 +61,8 @@ struct DevState {
     uint8_t *sk[2];               // bit 0 species, bits 1-2 kind
     void *acc, *alpha;            // [3][N], float or double
     void *aux;                    // [N][4]: V = m/rho, P/rho^2, 1/rho^2, V/S (0 if S = 0)
-    void *rhoP;                   // [N][2]: rho, P
+    void *rhoP;                   // [N][2]: rho, P (P before the pressure filter)
+    void *pf;                     // [N]: filtered pressure (instances with the filter on)
     uint32_t *key, *slot, *tmp, *pcell;
     uint32_t *idt;                // id of the particle at each scatter position (= id[tmp[.]])
     uint32_t *bframe;             // [n_bricks][128]: slot first indices, inclusive slot-count prefix
@@ -97,6 +103,11 @@ hipError_t launch_reorder(const DevState &d, const Launch &L, hipStream_t st, in
                           double kick, double dt);
 hipError_t launch_density(const DevState &d, const Launch &L, hipStream_t st);
 hipError_t launch_force(const DevState &d, const Launch &L, hipStream_t st);
+// Pressure filter after launch_density, for the instances that have it on.
+hipError_t launch_filter(const DevState &d, const Launch &L, hipStream_t st);
+// Collision step on the current (drifted, cell-ordered) state, for the instances that
+// have it on; uses the other velocity buffer as scratch.
+hipError_t launch_collide(const DevState &d, const Launch &L, hipStream_t st);
 hipError_t launch_load(const DevState &d, const Launch &L, hipStream_t st, const double *x,
                        const double *v, const double *w, const uint8_t *species,
                        const uint8_t *kind);

@@ -30,9 +30,10 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "sph4he.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(sph_params), offsetof(sph_params, dx),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(sph_params), offsetof(sph_params, dx),
          offsetof(sph_params, lo), offsetof(sph_params, mass), offsetof(sph_params, kappa_I),
-         offsetof(sph_params, cell_factor), sizeof(sph_tuning));
+         offsetof(sph_params, cell_factor), offsetof(sph_params, pressure_filter),
+         offsetof(sph_params, coll_alpha), offsetof(sph_params, coll_e), sizeof(sph_tuning));
   return 0;
 }
 """)
@@ -41,7 +42,8 @@ int main(void) {
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     P = L.SphParams
     want = [C.sizeof(P), P.dx.offset, P.lo.offset, P.mass.offset, P.kappa_I.offset,
-            P.cell_factor.offset, C.sizeof(L.SphTuning)]
+            P.cell_factor.offset, P.pressure_filter.offset, P.coll_alpha.offset,
+            P.coll_e.offset, C.sizeof(L.SphTuning)]
     assert got == want
 
 
@@ -80,6 +82,21 @@ def test_validation_rejects_bad_parameters():
     p.precision = 5
     assert _ws_status(p)[0] == L.E_INVALID
     assert _ws_status(_params(w), n=0)[0] == L.E_INVALID
+
+
+def test_validation_of_filter_and_collision_parameters():
+    w = I.make_cylinder(10)
+    h, dx = w.params["h"], w.params["dx"]
+    ok = dict(pressure_filter=1, coll_alpha=0.8, coll_e=0.3)
+    assert _ws_status(_params(w, **ok))[0] == L.OK
+    assert _ws_status(_params(w, pressure_filter=1, coll_alpha=0.0, coll_e=0.0))[0] == L.OK
+    for bad in (dict(pressure_filter=2), dict(pressure_filter=-1), dict(coll_alpha=-0.1),
+                dict(coll_alpha=2 * h / dx), dict(coll_alpha=float("inf")),
+                dict(coll_e=1.0 + 1e-12), dict(coll_e=-1e-12), dict(coll_e=float("nan"))):
+        assert _ws_status(_params(w, **dict(ok, **bad)))[0] == L.E_INVALID, bad
+    # the filtered pressure takes one more value per particle
+    n = 100000
+    assert _ws_status(_params(w, pressure_filter=1), n)[1] >= _ws_status(_params(w), n)[1] + 4 * n - 256
 
 
 def test_workspace_grows_with_particles():
