@@ -163,8 +163,10 @@ sph_status sph_init_particles(sph_sim *s, const double *x, const double *v,
  * (rad per unit time, about the z axis through x = y = 0; ignored when there are no wall
  * particles).  Per step: half kick and drift (walls rotated exactly), cell list, the
  * collision step (if enabled), density and EOS, the pressure filter (if enabled), pair
- * forces and torques, closing half kick (Algorithm 1).  The closing half kick is folded
- * into the next step's opening kick; reads apply it. */
+ * forces and torques, closing half kick (Algorithm 1).  The collision step changes only
+ * velocities, which the density and the filter do not read, so it is executed after them
+ * with the same result.  The closing half kick is folded into the next step's opening
+ * kick; reads apply it. */
 sph_status sph_step(sph_sim *s, double dt, double Omega, int32_t nsteps);
 
 /* Write the current fields by id; any pointer may be NULL to skip it.

@@ -699,14 +699,18 @@ __global__ void k_filter(DevState s)
 // summed over all such neighbours from the velocities before the step; the new velocities
 // go to the other velocity buffer (free between the reorder and the next step's) and
 // k_collide_apply copies them back.  Only cells within rc of the particle are walked
-// (rc < 2h; the test on each axis keeps a margin, so pruning never drops a pair).
-__global__ void k_collide(DevState s)
+// (rc < 2h; the test on each axis keeps a margin, so pruning never drops a pair).  With
+// `flagged`, only the particles the brick density sweep flagged as having a neighbour near
+// rc are tested (the others cannot collide).  Neither the density nor the pressure filter
+// reads velocities, so the step may run after them.
+__global__ void k_collide(DevState s, int flagged)
 {
     PIdx t = map_thread(s);
     if (!t.active) return;
     const InstDesc *d = t.d;
     if (!d->coll) return;
     const uint32_t N = s.N, p = t.p;
+    if (flagged && !s.cflag[p]) return;
     const int cur = s.cur;
     const uint8_t *SK = s.sk[cur];
     const uint8_t ski = SK[p];
@@ -784,13 +788,13 @@ __global__ void k_collide(DevState s)
     if (err) atomicOr(s.err, err);
 }
 
-__global__ void k_collide_apply(DevState s)
+__global__ void k_collide_apply(DevState s, int flagged)
 {
     PIdx t = map_thread(s);
     if (!t.active || !t.d->coll) return;
     const uint32_t N = s.N, p = t.p;
     const int cur = s.cur;
-    if ((s.sk[cur][p] >> 1) != KIND_FLUID) return;
+    if ((flagged && !s.cflag[p]) || (s.sk[cur][p] >> 1) != KIND_FLUID) return;
     for (int a = 0; a < 3; a++) s.v[cur][(size_t)a * N + p] = s.v[cur ^ 1][(size_t)a * N + p];
 }
 
@@ -1358,7 +1362,11 @@ __device__ __forceinline__ void test_targets(const float4 *stage, const float *p
     }
 }
 
-template <bool KAHAN>
+// With COLL, the sweep also flags (cflag) every target that has a neighbour within the
+// collision distance (plus a relative margin of 1e-4 on its square, far above the FP32
+// rounding of the staged distances), so that the collision step tests only those exactly.
+// Targets evaluated per particle (fallbacks) are flagged unconditionally.
+template <bool KAHAN, bool COLL>
 __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
 {
     __shared__ BrickFrame F;
@@ -1378,8 +1386,10 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
     if (!F.ok) {
         if (has_cell) {
             const uint32_t nt = F.off[tslot + 1] - F.off[tslot];
-            for (uint32_t i = lane; i < nt; i += 64)
+            for (uint32_t i = lane; i < nt; i += 64) {
                 err |= density_one<float, KAHAN>(s, d, F.begin[tslot] + i);
+                if (COLL) s.cflag[F.begin[tslot] + i] = 1;
+            }
         }
         if (err) atomicOr(s.err, err);
         return;
@@ -1393,7 +1403,10 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
     if (nt == 0) return;
     const StencilList S = stencil_list(F, ts, lane, &tbl[w][0][0]);
     if (S.NW > (uint32_t)kCandWin) {
-        for (uint32_t i = lane; i < nt; i += 64) err |= density_one<float, KAHAN>(s, d, pbase + i);
+        for (uint32_t i = lane; i < nt; i += 64) {
+            err |= density_one<float, KAHAN>(s, d, pbase + i);
+            if (COLL) s.cflag[pbase + i] = 1;
+        }
         if (err) atomicOr(s.err, err);
         return;
     }
@@ -1411,6 +1424,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
         }
     }
     const float cut2 = (float)(d->cut2 * d->inv_h * d->inv_h);  // positions in units of h
+    const float rc2m = (float)(d->coll_rc2 * d->inv_h * d->inv_h * (1.0 + 1e-4));
     const int kernel = d->kernel;
     // compiled once per smoothing kernel, chosen per brick (as in the force sweep)
     auto sweep = [&](auto kt) {
@@ -1467,6 +1481,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
             hit_share([&](int cc) { return mrow[cc]; }, act ? H : 0u, g, G, cnt, c, mc);
             const float4 me = stage[toff + t0 + tt];
             Acc<float, KAHAN> sw, su;
+            bool near = false;
             auto next_hit = [&]() {
                 while (mc == 0) mc = mrow[++c];
                 const int j = __builtin_ctzll(mc);
@@ -1479,9 +1494,11 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
             for (uint32_t i = 0; i < cnt; i++) {
                 const float4 qc = next_hit();
                 const float d0 = me.x - qc.x, d1 = me.y - qc.y, d2 = me.z - qc.z;
-                const float W = shape_W<KT>(d0 * d0 + d1 * d1 + d2 * d2);
+                const float r2s = d0 * d0 + d1 * d1 + d2 * d2;
+                const float W = shape_W<KT>(r2s);
                 sw.add(W);
                 su.add(qc.w != me.w ? W : 0.0f);
+                if (COLL) near |= r2s < rc2m;
             }
             const double SW = d->wnorm * group_total(sw.s, KAHAN ? sw.c : 0.0f, lane, (int)ntc, G);
             const double SU = d->wnorm * group_total(su.s, KAHAN ? su.c : 0.0f, lane, (int)ntc, G);
@@ -1489,6 +1506,13 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
                 const uint32_t p = pbase + t0 + tt;
                 const uint8_t ski = SK[p];
                 err |= density_finish<float>(s, d, p, ski & 1, ski >> 1, SW, SU);
+            }
+            if (COLL) {
+                // a target is near if any of its G lanes (tt, tt + ntc, ...) saw a near hit
+                const uint64_t nbal = __ballot(near);
+                uint64_t rep = 0;
+                for (int k = 0; k < G; k++) rep |= 1ull << (k * (int)ntc);
+                if (act && g == 0) s.cflag[pbase + t0 + tt] = ((nbal >> tt) & rep) != 0 ? 1 : 0;
             }
             wave_lds_handoff();  // the masks are rewritten by the next round
         }
@@ -2133,7 +2157,8 @@ hipError_t launch_density(const DevState &d, const Launch &L, hipStream_t st)
     if (d.precision == 0) k_density<double, false><<<g, L.bs_density, 0, st>>>(d);
     else if (L.sweep == SWEEP_CAND && d.n_bricks) {
         k_brick_frames<<<d.n_bricks, 64, 0, st>>>(d);
-        k_density_cand<true><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
+        if (d.any_coll) k_density_cand<true, true><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
+        else k_density_cand<true, false><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
     }
     else k_density<float, true><<<g, L.bs_density, 0, st>>>(d);
     return hipGetLastError();
@@ -2162,8 +2187,10 @@ hipError_t launch_collide(const DevState &d, const Launch &L, hipStream_t st)
 {
     if (!d.any_coll) return hipSuccess;
     unsigned g = grid_for(d.n_waves, L.bs_stream);
-    k_collide<<<g, L.bs_stream, 0, st>>>(d);
-    k_collide_apply<<<g, L.bs_stream, 0, st>>>(d);
+    // the brick density sweep (chosen as in launch_density) leaves the candidates flagged
+    const int flagged = (d.precision != 0 && L.sweep == SWEEP_CAND && d.n_bricks) ? 1 : 0;
+    k_collide<<<g, L.bs_stream, 0, st>>>(d, flagged);
+    k_collide_apply<<<g, L.bs_stream, 0, st>>>(d, flagged);
     return hipGetLastError();
 }
 

@@ -151,7 +151,7 @@ struct Carver {
 };
 
 void carve(Carver &c, DevState &d, int n_inst, uint32_t N, uint32_t C, uint32_t NB, int precision,
-           bool filter)
+           bool filter, bool coll)
 {
     size_t rs = precision == SPH_FP64 ? sizeof(double) : sizeof(float);
     size_t n3 = 3 * (size_t)N;
@@ -169,6 +169,7 @@ void carve(Carver &c, DevState &d, int n_inst, uint32_t N, uint32_t C, uint32_t 
     d.aux = c.take<char>(4 * (size_t)N * rs);
     d.rhoP = c.take<char>(2 * (size_t)N * rs);
     d.pf = c.take<char>((filter ? (size_t)N : 1) * rs);
+    d.cflag = c.take<uint8_t>(coll ? (size_t)N : 1);
     d.key = c.take<uint32_t>(N);
     d.slot = c.take<uint32_t>(N);
     d.tmp = c.take<uint32_t>(N);
@@ -405,8 +406,8 @@ sph_status prof_mark(sph_batch *b, int tag)
     return SPH_OK;
 }
 
-// One velocity Verlet step: opening kick + drift, cell list, collision step, density,
-// pressure filter, forces (the collision step and the filter for instances that have
+// One velocity Verlet step: opening kick + drift, cell list, density, pressure filter,
+// collision step, forces (the filter and the collision step for instances that have
 // them on; mode 0, the evaluation at load, has no collision step).
 sph_status enqueue_step(sph_batch *b, int mode, double kick, double dt)
 {
@@ -422,15 +423,18 @@ sph_status enqueue_step(sph_batch *b, int mode, double kick, double dt)
     if ((s = prof_mark(b, SPH_K_REORDER)) != SPH_OK) return s;
     if ((s = check_launch(b, launch_reorder(d, b->L, st, mode, kick, dt), "reorder")) != SPH_OK) return s;
     d.cur ^= 1;
-    if (mode == 1 && d.any_coll) {
-        if ((s = prof_mark(b, SPH_K_COLLIDE)) != SPH_OK) return s;
-        if ((s = check_launch(b, launch_collide(d, b->L, st), "collide")) != SPH_OK) return s;
-    }
     if ((s = prof_mark(b, SPH_K_DENSITY)) != SPH_OK) return s;
     if ((s = check_launch(b, launch_density(d, b->L, st), "density")) != SPH_OK) return s;
     if (d.any_filter) {
         if ((s = prof_mark(b, SPH_K_FILTER)) != SPH_OK) return s;
         if ((s = check_launch(b, launch_filter(d, b->L, st), "pressure filter")) != SPH_OK) return s;
+    }
+    // The collision step changes velocities only, which neither the density nor the
+    // filter reads: after them it gives the same state as before them, and the brick
+    // density sweep has flagged its candidates by then.
+    if (mode == 1 && d.any_coll) {
+        if ((s = prof_mark(b, SPH_K_COLLIDE)) != SPH_OK) return s;
+        if ((s = check_launch(b, launch_collide(d, b->L, st), "collide")) != SPH_OK) return s;
     }
     if ((s = prof_mark(b, SPH_K_FORCE)) != SPH_OK) return s;
     if ((s = check_launch(b, launch_force(d, b->L, st), "force")) != SPH_OK) return s;
@@ -616,7 +620,7 @@ sph_status sph_batch_workspace_bytes(int32_t n_inst, const sph_params *params,
     if (st != SPH_OK) return st;
     Carver c;
     DevState d{};
-    carve(c, d, n_inst, pl.N, pl.C, pl.n_bricks, params[0].precision, pl.any_filter);
+    carve(c, d, n_inst, pl.N, pl.C, pl.n_bricks, params[0].precision, pl.any_filter, pl.any_coll);
     *bytes = c.off;
     return SPH_OK;
 }
@@ -636,7 +640,7 @@ sph_status sph_batch_create(int32_t n_inst, const sph_params *params, const int6
     if (st != SPH_OK) return st;
     Carver c;
     DevState d{};
-    carve(c, d, n_inst, pl.N, pl.C, pl.n_bricks, params[0].precision, pl.any_filter);
+    carve(c, d, n_inst, pl.N, pl.C, pl.n_bricks, params[0].precision, pl.any_filter, pl.any_coll);
     if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || ws_bytes < c.off) return SPH_E_WORKSPACE;
     sph_batch *b = new (std::nothrow) sph_batch();
     if (!b) return SPH_E_INVALID;
@@ -647,7 +651,7 @@ sph_status sph_batch_create(int32_t n_inst, const sph_params *params, const int6
     b->steptab.assign(n_inst, StepParams{1.0, 0.0, 0.0, 0.0});
     Carver c2;
     c2.base = (char *)workspace;
-    carve(c2, b->ds, n_inst, pl.N, pl.C, pl.n_bricks, params[0].precision, pl.any_filter);
+    carve(c2, b->ds, n_inst, pl.N, pl.C, pl.n_bricks, params[0].precision, pl.any_filter, pl.any_coll);
     b->ds.precision = params[0].precision;
     b->ds.n_inst = n_inst;
     b->ds.cur = 0;
