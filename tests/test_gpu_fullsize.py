@@ -172,6 +172,62 @@ def test_cylinder_19p57M_mixed_one_step(cyl1957):
         assert e[k] < 1e-5, (k, e[k])
 
 
+F1 = dict(pressure_filter=1, coll_alpha=0.8, coll_e=0.3)
+
+
+def test_cylinder_19p57M_filtered_initial_fields(cyl1957):
+    """The benchmarked workload with the pressure filter and the collision step on (the
+    configuration of the benchmark's filter-and-collision leg): sampled particles against
+    the oracle's one-by-one evaluation (densities of two rings around the sample, filtered
+    pressures of one, then the sample's forces)."""
+    w = copy.copy(cyl1957)
+    w.params = dict(w.params, **F1)
+    rng = np.random.default_rng(13)
+    fluid = np.nonzero(w.kind == I.FLUID)[0]
+    near_wall = fluid[np.hypot(w.x[0, fluid], w.x[1, fluid]) > 1.0 - 6 * w.params["dx"]]
+    idx = np.unique(np.concatenate([rng.choice(fluid, 1500, replace=False),
+                                    rng.choice(near_wall, 500, replace=False)]))
+    rho, P, S_, acc, alpha = O.eval_subset(w.params, w.x, w.v, w.omega, w.species, w.kind, idx)
+    B = w.params["rho0"] * w.params["c0"] ** 2 / 7.0
+    s = _sim(w, L.FP32_MIXED, "cylinder_nz184")
+    out = s.read(("rho", "P", "acc", "alpha"))
+    s.close()
+    del s
+    e_P = np.abs(out["P"][idx] - P).max() / B
+    na = np.sqrt((acc ** 2).sum(0)).max()
+    e_acc = np.sqrt(((out["acc"][:, idx] - acc) ** 2).sum(0)).max() / na
+    print(f"19.57M filtered sampled: P {e_P:.2e} acc {e_acc:.2e}", flush=True)
+    assert max(e_P, e_acc) < 1e-5
+
+
+def test_cylinder_19p57M_jittered_step_with_collisions(cyl1957):
+    """Every particle after one step of the 19.57M cylinder with its fluid jittered by up
+    to 0.3 dx, so that millions of pairs come within the collision distance, against the
+    oracle's step, in the benchmarked launch configuration."""
+    w = copy.copy(cyl1957)
+    rng = np.random.default_rng([3980, 77])
+    f = w.kind == I.FLUID
+    x = w.x.copy()
+    x[:, f] += rng.uniform(-0.3, 0.3, size=(3, int(f.sum()))) * w.params["dx"]
+    x[2] = np.mod(x[2], 1.0)
+    v = w.v.copy()
+    v[:, f] += rng.normal(0.0, 0.05, size=(3, int(f.sum())))
+    w.x, w.v = x, v
+    w.params = dict(w.params, **F1)
+    s = _sim(w, L.FP32_MIXED, "cylinder_nz184")
+    s.step(1e-4, w.Omega, 1)
+    out = s.read(("x", "v", "omega", "rho", "P"))
+    s.close()
+    del s
+    ref = O.State.from_workload(w)
+    ref.step(1e-4, w.Omega, 1)
+    e = field_errors(out, ref, w)
+    print("19.57M jittered, filter + collisions, 1 step", e, flush=True)
+    assert positions_ok(e, 1e-5, 1), e
+    for k in ("v", "omega", "rho", "P"):
+        assert e[k] < 1e-5, (k, e[k])
+
+
 def test_batch64_equals_single_instances():
     """The 64-instance ensemble (5.9M particles) in its tuned launch configuration equals,
     bit for bit, each instance run on its own with the same settings."""
