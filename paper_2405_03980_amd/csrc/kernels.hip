@@ -1680,9 +1680,9 @@ __device__ __forceinline__ void stage_filter(const DevState &s, const BrickFrame
 // Pressure filter over the brick sweeps' neighbour masks (the density sweep's, replayed as
 // in the force sweep): lanes = (target, group g of G) over the block's fluid and
 // inner-wall targets; outer walls copy their fixed pressure directly.  The kernel shape
-// sums are scaled by the normalisation in FP64, where the self term joins them; the
-// stage capacity is the force sweep's, so a brick the density sweep could not stage (and
-// left without masks) is filtered per particle here too.
+// sums are scaled by the normalisation in FP64, where the self term joins the denominator;
+// the stage capacity is the force sweep's, so a brick the density sweep could not stage
+// (and left without masks) is filtered per particle here too.
 template <bool KAHAN>
 __global__ void __launch_bounds__(kBrickThreads, 4) k_filter_cand(DevState s)
 {
@@ -1746,22 +1746,27 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_filter_cand(DevState s)
             const uint32_t t = (uint32_t)__builtin_ctzll(drop_low_bits(Mt, (uint32_t)(lane % n)));
             const uint32_t p = pbase + t0 + t;
             const float4 Ai = SA[toff + t0 + t];
+            const float Pi = RP[2 * (size_t)p + 1];
             HitReplay hr(s.masks + (size_t)p * kMaskSlots, NW, target, g, G);
-            Acc<float, KAHAN> num, den;
+            // P~ = P_i + sum V_j (P_j - P_i) W_ij / (V_i W(0) + sum V_j W_ij): the numerator
+            // holds only pressure differences (compensated); the denominator's terms are all
+            // positive and it scales only that difference, so it is summed plainly
+            Acc<float, KAHAN> num;
+            float den = 0.0f;
 #pragma unroll 2
             for (uint32_t i = 0; i < hr.cnt; i++) {
                 const uint32_t k = hr.next(tbl[w]);
                 const float4 A = SA[k];
                 const float d0 = Ai.x - A.x, d1 = Ai.y - A.y, d2 = Ai.z - A.z;
                 const float W = shape_W<KT>(d0 * d0 + d1 * d1 + d2 * d2);
-                num.add(SP[k] * W);
-                den.add(A.w * W);
+                num.add(fmaf(-A.w, Pi, SP[k]) * W);
+                den = fmaf(A.w, W, den);
             }
             const double sn = group_total(num.s, KAHAN ? num.c : 0.0f, lane, n, G);
-            const double sd = group_total(den.s, KAHAN ? den.c : 0.0f, lane, n, G);
+            const double sd = group_total(den, 0.0f, lane, n, G);
             if (target && g == 0) {
-                const double Vp = (double)AUX[4 * (size_t)p], Pp = (double)RP[2 * (size_t)p + 1];
-                const double Pt = (Vp * Pp * W0 + wn * sn) / (Vp * W0 + wn * sd);
+                const double Vp = (double)AUX[4 * (size_t)p], Pp = (double)Pi;
+                const double Pt = Pp + wn * sn / (Vp * W0 + wn * sd);
                 PF[p] = (float)Pt;
                 AUX[4 * (size_t)p + 1] = (float)(Pt * (double)AUX[4 * (size_t)p + 2]);
                 if (!isfinite(Pt)) err |= ERR_NONFINITE;
