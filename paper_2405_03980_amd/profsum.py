@@ -6,7 +6,8 @@ Reads one sub-directory per rocprofv3 run under a root folder:
 * ``fetch`` / ``write`` -- ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` of the benchmark;
 * ``copyf`` / ``copyw`` -- the same two counters over a plain 1 GiB device copy, which
   fix the factor between each counter and true bytes;
-* ``sq`` -- one pass of SQ_* counters.
+* ``sq`` -- one pass of SQ_* instruction counters;
+* ``sq2`` -- one pass of SQ_* wait counters (where a kernel's waves spend their cycles).
 
 Prints a text summary; with a second argument writes the per-kernel HBM traffic (KiB per
 dispatch plus the copy calibration) as JSON, stamped with a hash of the kernel sources so
@@ -27,10 +28,13 @@ import sys
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-BENCH = "python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline --fp64-steps 0 --batch-steps 0"
+BENCH = ("python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline --fp64-steps 0 --batch-steps 0 "
+         "--f1-steps 3")
 COPY = "python3 bench.py --copy-calibration 1024"
 SQ = ("SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_SALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES "
       "SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_VALU")
+SQ2 = ("SQ_WAVES SQ_WAVE_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_WAIT_INST_LDS SQ_INSTS_VMEM_RD "
+       "SQ_INST_CYCLES_VMEM_RD SQ_LDS_IDX_ACTIVE")
 # One rocprofv3 run per sub-directory, from the repository root, with TMPDIR=/tmp.
 COMMANDS = [
     ("trace", f"rocprofv3 --kernel-trace --stats -d gpurun_out/prof/trace -o run -- {BENCH}"),
@@ -39,13 +43,16 @@ COMMANDS = [
     ("copyf", f"rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof/copyf -o run -- {COPY}"),
     ("copyw", f"rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof/copyw -o run -- {COPY}"),
     ("sq", f"rocprofv3 --pmc {SQ} -d gpurun_out/prof/sq -o run -- {BENCH}"),
+    ("sq2", f"rocprofv3 --pmc {SQ2} -d gpurun_out/prof/sq2 -o run -- {BENCH}"),
 ]
 # VALU instruction issue capacity: 256 CUs x 4 SIMDs, one wave64 instruction per 4 cycles
 # on a 16-lane SIMD, at 2.4 GHz.
 VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
 COPY_MIB = 1024
 KERNEL_GROUPS = {"k_keys<float>": "keys", "k_scatter": "scatter", "k_reorder<float>": "reorder",
-                 "k_density_cand<true>": "density", "k_force_cand<true>": "force"}
+                 "k_density_cand<true, false>": "density", "k_force_cand<true>": "force",
+                 "k_density_cand<true, true>": "density_flagging", "k_filter_cand<true>": "filter",
+                 "k_collide": "collide"}
 
 
 def source_sha() -> str:
@@ -111,6 +118,8 @@ def summarize(root: str, out_json: str | None = None, workload: str = "",
         for kname, group in KERNEL_GROUPS.items():
             if kname in allc.get("sq", {}) and group not in sq:
                 sq[group] = {cn: sum(v) / len(v) for cn, v in allc["sq"][kname].items()}
+            if kname in allc.get("sq2", {}) and group in sq:
+                sq[group].update({f"{cn}@2": sum(v) / len(v) for cn, v in allc["sq2"][kname].items()})
         res = {"source_sha": source_sha(), "fetch_scale": kib / cf, "write_scale": kib / cw,
                "copy_MiB": COPY_MIB, "copy_FETCH_SIZE_KiB": cf, "copy_WRITE_SIZE_KiB": cw,
                "kernels": kern, "sq": sq, "workload": workload}
@@ -161,6 +170,19 @@ def _markdown(res: dict, trace: list) -> str:
         util = f"{100 * c['SQ_INSTS_VALU'] / (us * 1e-6 * VALU_ISSUE_PER_S):.0f}%" if us else "-"
         out.append(f"| {g} | {c['SQ_INSTS_VALU']:.3e} | {c['SQ_INSTS_SALU']:.3e} | "
                    f"{c['SQ_INSTS_LDS']:.3e} | {c['SQ_LDS_BANK_CONFLICT']:.3e} | {util} |")
+    waits = {g: c for g, c in res["sq"].items() if "SQ_WAVE_CYCLES@2" in c}
+    if waits:
+        out += ["", "## Where the waves wait (second SQ pass)", "",
+                "Fractions of SQ_WAVE_CYCLES (summed over waves) spent waiting on anything, "
+                "waiting to issue, and waiting on LDS instructions; vector memory reads per "
+                "wave.", "",
+                "| group | wait any | wait inst any | wait inst LDS | VMEM reads per wave |",
+                "|---|---|---|---|---|"]
+        for g, c in waits.items():
+            wc = c["SQ_WAVE_CYCLES@2"] or 1.0
+            out.append(f"| {g} | {c['SQ_WAIT_ANY@2'] / wc:.2f} | {c['SQ_WAIT_INST_ANY@2'] / wc:.2f} | "
+                       f"{c['SQ_WAIT_INST_LDS@2'] / wc:.2f} | "
+                       f"{c['SQ_INSTS_VMEM_RD@2'] / max(c['SQ_WAVES@2'], 1.0):.1f} |")
     return "\n".join(out) + "\n"
 
 
