@@ -9,12 +9,15 @@
 //              cell-sorted order (the paper's periodic defragmentation, done every step);
 //   density    kernel-summed density, Tait EOS (Eq. 4) and the per-particle factors the
 //              force sweep needs;
+//   filter     pressure filter of Algorithm 1 (when enabled);
+//   collide    collision step of Algorithm 1 (when enabled; it changes velocities only,
+//              which the density and the filter do not read, so it runs after them);
 //   force      pair forces of Eqs. 1-2 and the spin torques.
-// The density and force sweeps come in two forms: one thread per particle (k_density,
-// k_force; the FP64 path), and one that stages a 2x2x2-cell brick's neighbourhood in LDS
-// and tests candidates with wave ballots (k_density_cand, k_force_cand, after
-// k_brick_frames; the FP32-mixed default with cell factor 1).
-// The closing half kick is folded into the next k_keys / k_reorder.
+// The density, filter and force sweeps come in two forms: one thread per particle
+// (k_density, k_filter, k_force; the FP64 path), and one that stages a 2x2x2-cell brick's
+// neighbourhood in LDS and tests candidates with wave ballots (k_density_cand,
+// k_filter_cand, k_force_cand, after k_brick_frames; the FP32-mixed default with cell
+// factor 1).  The closing half kick is folded into the next k_keys / k_reorder.
 #include <math.h>
 #include <type_traits>
 
@@ -1197,9 +1200,9 @@ __device__ __forceinline__ void pair_force_f32(const PairK &k, const PairI &I, f
 // in registers as windows of 64 candidates, one per lane.  Testing one target against a
 // window is then one 64-lane comparison whose ballot is the window's hit mask, so targets
 // are tested one after another with every lane busy.  The density sweep stores the masks
-// (one word per window and target) and the force sweep replays them.  Pair terms are
-// evaluated with lanes = (target, group g of G): group g takes the g-th of G equal
-// consecutive shares of the target's hits in list order.
+// (one word per window and target); the pressure filter and the force sweep replay them.
+// Pair terms are evaluated with lanes = (target, group g of G): group g takes the g-th of
+// G equal consecutive shares of the target's hits in list order.
 
 constexpr int kCandWin = 10;      // windows per wave: stencils of up to 640 candidates
 constexpr int kListTargets = 32;  // targets per round of the density sweep (masks in LDS)
@@ -1335,7 +1338,7 @@ struct HitReplay {
 // Ballot tests of targets kbase .. kbase + ntc - 1 (staged indices) against the first NWc
 // candidate windows, NWc fixed at compile time so that the windows need no branch per
 // target.  The ballots of one target stay in scalar registers until lane t copies them
-// into mlo/mhi (low and high halves) in one masked pass.
+// into mw, one 64-bit move per window.
 // The test is |c - t|^2 < cut2 expanded as |c|^2 - 2 c.t < cut2 - |t|^2, with the
 // candidate's -2c (px, py, pz) and |c|^2 (cc) precomputed: three FMAs and a compare per
 // target and window.  Positions are relative to the brick centre in units of h

@@ -78,7 +78,8 @@ struct DevState {
     uint32_t *brick_xyz, *brick_inst;
     uint32_t n_bricks;
     // Neighbour hit masks of the brick sweeps, kMaskSlots per particle: the density sweep
-    // records the windows of candidate tests, the force sweep replays them.
+    // records the windows of candidate tests, the pressure filter and the force sweep
+    // replay them.
     uint64_t *masks;
 };
 
