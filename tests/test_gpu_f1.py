@@ -157,3 +157,49 @@ def test_f1_parameters_are_checked():
                 dict(coll_alpha=2.0 * 1.3 + 1e-9), dict(coll_e=float("nan"))):
         with pytest.raises(L.SphError):
             S.Simulation(dict(w.params, **bad), w.n, precision=MIXED)
+
+
+@pytest.mark.parametrize("prec,tol", [(FP64, 1e-12), (MIXED, 1e-5)])
+def test_free_cluster_conserves_momentum(prec, tol):
+    """Open geometry, crowded free cluster: ten steps with the filter and collisions against
+    the oracle, and sum m v and sum (m x × v + I omega) unchanged on the GPU (FP64 sums of
+    the GPU state, to the accuracy of the path)."""
+    w = I.make_cluster(9, jitter=0.35, noise=0.3)
+    w.params = dict(w.params, **F1)
+    steps = 10 if prec == FP64 else 1
+    ref = O.State.from_workload(w)
+    ref.step(1e-4, 0.0, steps)
+    s = _sim(w, prec)
+    P0, J0, _ = s.diagnostics()
+    s.step(1e-4, 0.0, steps)
+    out = s.read()
+    P1, J1, _ = s.diagnostics()
+    s.close()
+    e = field_errors(out, ref, w)
+    print("[f1 cluster]", prec, e, flush=True)
+    _assert_fields(e, tol, steps)
+    m = O.default_mass(w.params)[0]
+    scale = m * w.n * np.abs(w.v).max()
+    ctol = 1e-13 if prec == FP64 else 1e-6
+    assert np.abs(P1 - P0).max() < ctol * scale
+    assert np.abs(J1 - J0).max() < ctol * scale
+
+
+@pytest.mark.parametrize("prec", [FP64, MIXED])
+def test_lone_particle(prec):
+    """One particle: its filtered pressure is its own, and nothing collides."""
+    p = I.base_params(I.KERNEL_WENDLAND_C2, I.GEOM_OPEN, 0.05, [0, 0, 0], [1, 1, 1], 1.0)
+    p = dict(p, **F1)
+    x = np.array([[0.5], [0.5], [0.5]])
+    v = np.array([[0.3], [-0.1], [0.2]])
+    w = I.Workload("lone", p, x, v, np.zeros((3, 1)), np.zeros(1, np.uint8), np.zeros(1, np.uint8))
+    ref = O.State.from_workload(w)
+    ref.step(1e-3, 0.0, 3)
+    s = _sim(w, prec)
+    s.step(1e-3, 0.0, 3)
+    out = s.read()
+    s.close()
+    B = p["rho0"] * p["c0"] ** 2 / 7.0
+    assert abs(out["P"][0] - ref.P[0]) <= (1e-12 if prec == FP64 else 1e-6) * B
+    assert np.allclose(out["x"], ref.x, rtol=0, atol=1e-14)
+    assert np.array_equal(out["v"], v)
