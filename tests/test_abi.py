@@ -99,6 +99,24 @@ def test_validation_of_filter_and_collision_parameters():
     assert _ws_status(_params(w, pressure_filter=1), n)[1] >= _ws_status(_params(w), n)[1] + 4 * n - 256
 
 
+def test_size_limits():
+    """Up to 2^30 particles over all instances and 1024 cells per axis; the workspace size
+    is computed without touching a device."""
+    w = I.make_cylinder(10)
+    st, nb = _ws_status(_params(w), 1 << 30)
+    assert st == L.OK and nb > (1 << 30) * 200
+    assert _ws_status(_params(w), (1 << 30) + 1)[0] == L.E_INVALID
+    # a cell grid of more than 1024 cells along an axis
+    assert _ws_status(_params(w, h=1.0 / 4000.0, dx=1.0 / 5200.0))[0] == L.E_INVALID
+    # a batch whose instances together exceed 2^30 particles
+    P = (L.SphParams * 2)(_params(w), _params(w))
+    counts = (C.c_int64 * 2)(1 << 29, (1 << 29) + 1)
+    nb = C.c_size_t(0)
+    assert L.lib().sph_batch_workspace_bytes(2, P, counts, C.byref(nb)) == L.E_INVALID
+    counts = (C.c_int64 * 2)(1 << 29, 1 << 29)
+    assert L.lib().sph_batch_workspace_bytes(2, P, counts, C.byref(nb)) == L.OK
+
+
 def test_workspace_grows_with_particles():
     w = I.make_cylinder(10)
     p = _params(w)
