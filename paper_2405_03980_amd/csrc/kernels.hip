@@ -119,23 +119,24 @@ __device__ __forceinline__ uint32_t morton3(uint32_t x, uint32_t y, uint32_t z)
     return k;
 }
 
-// Calls fn(begin, end) for the sorted-particle range of every cell within +-cf of
-// (cx, cy, cz), wrapping periodic axes and skipping cells off a bounded axis.
+// Calls fn(begin, end) for the sorted-particle range of every cell at offsets
+// [lo[a], hi[a]] (within +-cf) from (cx, cy, cz), wrapping periodic axes and skipping cells
+// off a bounded axis.
 template <class Fn>
-__device__ __forceinline__ void for_each_cell(const DevState &s, const InstDesc *d, int cx,
-                                              int cy, int cz, uint32_t &err, Fn &&fn)
+__device__ __forceinline__ void for_cells_in(const DevState &s, const InstDesc *d, int cx, int cy,
+                                             int cz, const int lo[3], const int hi[3],
+                                             uint32_t &err, Fn &&fn)
 {
-    const int cf = d->cf;
     const int n0 = d->n[0], n1 = d->n[1], n2 = d->n[2];
-    for (int oz = -cf; oz <= cf; ++oz) {
+    for (int oz = lo[2]; oz <= hi[2]; ++oz) {
         int z = cz + oz;
         if (d->periodic[2]) { z += z < 0 ? n2 : 0; z -= z >= n2 ? n2 : 0; }
         else if (z < 0 || z >= n2) continue;
-        for (int oy = -cf; oy <= cf; ++oy) {
+        for (int oy = lo[1]; oy <= hi[1]; ++oy) {
             int y = cy + oy;
             if (d->periodic[1]) { y += y < 0 ? n1 : 0; y -= y >= n1 ? n1 : 0; }
             else if (y < 0 || y >= n1) continue;
-            for (int ox = -cf; ox <= cf; ++ox) {
+            for (int ox = lo[0]; ox <= hi[0]; ++ox) {
                 int x = cx + ox;
                 if (d->periodic[0]) { x += x < 0 ? n0 : 0; x -= x >= n0 ? n0 : 0; }
                 else if (x < 0 || x >= n0) continue;
@@ -147,6 +148,16 @@ __device__ __forceinline__ void for_each_cell(const DevState &s, const InstDesc 
             }
         }
     }
+}
+
+// The same over the whole stencil, +-cf cells on every axis.
+template <class Fn>
+__device__ __forceinline__ void for_each_cell(const DevState &s, const InstDesc *d, int cx,
+                                              int cy, int cz, uint32_t &err, Fn &&fn)
+{
+    const int cf = d->cf;
+    const int lo[3] = {-cf, -cf, -cf}, hi[3] = {cf, cf, cf};
+    for_cells_in(s, d, cx, cy, cz, lo, hi, err, fn);
 }
 
 // ------------------------------------------------------------ integrator pieces -----
@@ -739,50 +750,32 @@ __global__ void k_collide(DevState s, int flagged)
     }
     const double mi = d->mass[ski & 1];
     const double rc2 = d->coll_rc2, e1 = d->coll_e1;
-    const int n0 = d->n[0], n1 = d->n[1], n2 = d->n[2];
     uint32_t err = 0;
     double dv[3] = {0.0, 0.0, 0.0};
-    for (int oz = olo[2]; oz <= ohi[2]; ++oz) {
-        int z = c[2] + oz;
-        if (d->periodic[2]) { z += z < 0 ? n2 : 0; z -= z >= n2 ? n2 : 0; }
-        else if (z < 0 || z >= n2) continue;
-        for (int oy = olo[1]; oy <= ohi[1]; ++oy) {
-            int y = c[1] + oy;
-            if (d->periodic[1]) { y += y < 0 ? n1 : 0; y -= y >= n1 ? n1 : 0; }
-            else if (y < 0 || y >= n1) continue;
-            for (int ox = olo[0]; ox <= ohi[0]; ++ox) {
-                int x = c[0] + ox;
-                if (d->periodic[0]) { x += x < 0 ? n0 : 0; x -= x >= n0 ? n0 : 0; }
-                else if (x < 0 || x >= n0) continue;
-                const uint32_t lin = (uint32_t)x + (uint32_t)n0 * ((uint32_t)y + (uint32_t)n1 * (uint32_t)z);
-                const uint32_t r = s.rank_of_lin[d->cell_off + lin];
-                const uint32_t b = s.start[r], e = s.start[r + 1];
-                if (e - b > (uint32_t)kMaxCell) { err |= ERR_CAPACITY; continue; }
-                for (uint32_t q = b; q < e; ++q) {
-                    if (q == p) continue;
-                    const double r0 = min_img(d, 0, xi[0] - X[q]);
-                    const double r1 = min_img(d, 1, xi[1] - X[N + q]);
-                    const double rr2 = min_img(d, 2, xi[2] - X[2 * N + q]);
-                    const double d2 = r2_exact(r0, r1, rr2);
-                    if (!(d2 < rc2)) continue;
-                    double vn;
-                    {
+    for_cells_in(s, d, c[0], c[1], c[2], olo, ohi, err, [&](uint32_t b, uint32_t e) {
+        for (uint32_t q = b; q < e; ++q) {
+            if (q == p) continue;
+            const double r0 = min_img(d, 0, xi[0] - X[q]);
+            const double r1 = min_img(d, 1, xi[1] - X[N + q]);
+            const double rr2 = min_img(d, 2, xi[2] - X[2 * N + q]);
+            const double d2 = r2_exact(r0, r1, rr2);
+            if (!(d2 < rc2)) continue;
+            double vn;
+            {
 #pragma clang fp contract(off)
-                        vn = (vi[0] - Vv[q]) * r0;
-                        vn = vn + (vi[1] - Vv[N + q]) * r1;
-                        vn = vn + (vi[2] - Vv[2 * N + q]) * rr2;
-                    }
-                    if (!(vn < 0.0)) continue;
-                    const uint8_t skq = SK[q];
-                    const double mu = (skq >> 1) == KIND_FLUID ? d->mass[skq & 1] / (mi + d->mass[skq & 1]) : 1.0;
-                    const double g = -e1 * mu * vn / d2;
-                    dv[0] += g * r0;
-                    dv[1] += g * r1;
-                    dv[2] += g * rr2;
-                }
+                vn = (vi[0] - Vv[q]) * r0;
+                vn = vn + (vi[1] - Vv[N + q]) * r1;
+                vn = vn + (vi[2] - Vv[2 * N + q]) * rr2;
             }
+            if (!(vn < 0.0)) continue;
+            const uint8_t skq = SK[q];
+            const double mu = (skq >> 1) == KIND_FLUID ? d->mass[skq & 1] / (mi + d->mass[skq & 1]) : 1.0;
+            const double g = -e1 * mu * vn / d2;
+            dv[0] += g * r0;
+            dv[1] += g * r1;
+            dv[2] += g * rr2;
         }
-    }
+    });
     for (int a = 0; a < 3; a++) {
         const double vnew = vi[a] + dv[a];
         VN[(size_t)a * N + p] = vnew;
