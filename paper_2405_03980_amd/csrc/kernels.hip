@@ -1002,12 +1002,36 @@ __device__ __forceinline__ void stage_density(const DevState &s, const BrickFram
     }
 }
 
+// Spreads the brick's M staged particles over the workgroup, up to three per thread (k,
+// k + 512, k + 1024 from threadIdx.x), spaced evenly over the neighbourhood: load(u, q)
+// issues the loads of particle u (sorted index q) for all three first, so that they are in
+// flight together, then store(u, k, slot) writes staged particle k of that slot.
+template <class Load, class Store>
+__device__ __forceinline__ void stage_spread(const BrickFrame &F, uint32_t M, Load &&load,
+                                             Store &&store)
+{
+    for (uint32_t k0 = threadIdx.x; k0 < M; k0 += 3 * kBrickThreads) {
+        uint32_t kk[3], qq[3];
+        int sl[3];
+        for (int u = 0; u < 3; u++) {
+            kk[u] = k0 + (uint32_t)u * kBrickThreads;
+            sl[u] = slot_of(F, min(kk[u], M - 1));
+            qq[u] = F.begin[sl[u]] + (min(kk[u], M - 1) - F.off[sl[u]]);
+        }
+        for (int u = 0; u < 3; u++) load(u, qq[u]);
+        for (int u = 0; u < 3; u++) {
+            if (kk[u] >= M) break;
+            store(u, kk[u], sl[u]);
+        }
+    }
+}
+
 // Stages what the force sweep reads of the brick's M neighbourhood particles: position
 // relative to the brick centre and P/rho^2; velocity relative to vref and V (negative for
 // the viscous species); half the spin (exact, so (w_i + w_j)/2 takes one add) and V/S.
-// Positions and velocities are in units of h (ih = 1/h, applied in FP64).  Each thread
-// takes up to three particles spread evenly over the neighbourhood (the heavier force
-// staging prefers this to whole slots).
+// Positions and velocities are in units of h (ih = 1/h, applied in FP64).  Particles are
+// spread over the threads by stage_spread (the heavier force staging prefers this to
+// whole slots).
 __device__ __forceinline__ void stage_force(const DevState &s, const BrickFrame &F, uint32_t M,
                                             const double *vref, double ih, float4 *SA, float4 *SB,
                                             float4 *SC)
@@ -1017,39 +1041,26 @@ __device__ __forceinline__ void stage_force(const DevState &s, const BrickFrame 
     const double *X = s.x[cur], *Vv = s.v[cur], *Ww = s.w[cur];
     const uint8_t *SK = s.sk[cur];
     const float *AUX = (const float *)s.aux;
-    for (uint32_t k0 = threadIdx.x; k0 < M; k0 += 3 * kBrickThreads) {
-        uint32_t kk[3], qq[3];
-        int sl[3];
-        for (int u = 0; u < 3; u++) {
-            kk[u] = k0 + (uint32_t)u * kBrickThreads;
-            sl[u] = slot_of(F, min(kk[u], M - 1));
-            qq[u] = F.begin[sl[u]] + (min(kk[u], M - 1) - F.off[sl[u]]);
+    double px[3][3], pv[3][3], pw[3][3];
+    float4 aq[3];
+    uint8_t sk[3];
+    stage_spread(F, M, [&](int u, uint32_t q) {
+        for (int a = 0; a < 3; a++) {
+            px[u][a] = X[(size_t)a * N + q];
+            pv[u][a] = Vv[(size_t)a * N + q];
+            pw[u][a] = Ww[(size_t)a * N + q];
         }
-        double px[3][3], pv[3][3], pw[3][3];
-        float4 aq[3];
-        uint8_t sk[3];
-        for (int u = 0; u < 3; u++) {
-            const uint32_t q = qq[u];
-            for (int a = 0; a < 3; a++) {
-                px[u][a] = X[(size_t)a * N + q];
-                pv[u][a] = Vv[(size_t)a * N + q];
-                pw[u][a] = Ww[(size_t)a * N + q];
-            }
-            aq[u] = *(const float4 *)(AUX + 4 * (size_t)q);
-            sk[u] = SK[q];
-        }
-        for (int u = 0; u < 3; u++) {
-            if (kk[u] >= M) break;
-            const uint32_t k = kk[u];
-            SA[k] = make_float4((float)(((px[u][0] + F.shift[sl[u]][0]) - F.origin[0]) * ih),
-                                (float)(((px[u][1] + F.shift[sl[u]][1]) - F.origin[1]) * ih),
-                                (float)(((px[u][2] + F.shift[sl[u]][2]) - F.origin[2]) * ih), aq[u].y);
-            SB[k] = make_float4((float)((pv[u][0] - vref[0]) * ih), (float)((pv[u][1] - vref[1]) * ih),
-                                (float)((pv[u][2] - vref[2]) * ih), (sk[u] & 1) ? -aq[u].x : aq[u].x);
-            SC[k] = make_float4((float)(0.5 * pw[u][0]), (float)(0.5 * pw[u][1]), (float)(0.5 * pw[u][2]),
-                                aq[u].w);
-        }
-    }
+        aq[u] = *(const float4 *)(AUX + 4 * (size_t)q);
+        sk[u] = SK[q];
+    }, [&](int u, uint32_t k, int sl) {
+        SA[k] = make_float4((float)(((px[u][0] + F.shift[sl][0]) - F.origin[0]) * ih),
+                            (float)(((px[u][1] + F.shift[sl][1]) - F.origin[1]) * ih),
+                            (float)(((px[u][2] + F.shift[sl][2]) - F.origin[2]) * ih), aq[u].y);
+        SB[k] = make_float4((float)((pv[u][0] - vref[0]) * ih), (float)((pv[u][1] - vref[1]) * ih),
+                            (float)((pv[u][2] - vref[2]) * ih), (sk[u] & 1) ? -aq[u].x : aq[u].x);
+        SC[k] = make_float4((float)(0.5 * pw[u][0]), (float)(0.5 * pw[u][1]), (float)(0.5 * pw[u][2]),
+                            aq[u].w);
+    });
 }
 
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -1632,8 +1643,7 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
 
 // Stages what the pressure filter reads of the brick's M neighbourhood particles: the
 // position relative to the brick centre in units of h with the source volume V (0 for an
-// outer wall, which is not a source), and V P.  Spread over the threads as in
-// stage_force.
+// outer wall, which is not a source), and V P.
 __device__ __forceinline__ void stage_filter(const DevState &s, const BrickFrame &F, uint32_t M,
                                              double ih, float4 *SA, float *SP)
 {
@@ -1643,34 +1653,21 @@ __device__ __forceinline__ void stage_filter(const DevState &s, const BrickFrame
     const uint8_t *SK = s.sk[cur];
     const float *AUX = (const float *)s.aux;
     const float *RP = (const float *)s.rhoP;
-    for (uint32_t k0 = threadIdx.x; k0 < M; k0 += 3 * kBrickThreads) {
-        uint32_t kk[3], qq[3];
-        int sl[3];
-        for (int u = 0; u < 3; u++) {
-            kk[u] = k0 + (uint32_t)u * kBrickThreads;
-            sl[u] = slot_of(F, min(kk[u], M - 1));
-            qq[u] = F.begin[sl[u]] + (min(kk[u], M - 1) - F.off[sl[u]]);
-        }
-        double px[3][3];
-        float vq[3], pq[3];
-        uint8_t sk[3];
-        for (int u = 0; u < 3; u++) {
-            const uint32_t q = qq[u];
-            for (int a = 0; a < 3; a++) px[u][a] = X[(size_t)a * N + q];
-            vq[u] = AUX[4 * (size_t)q];
-            pq[u] = RP[2 * (size_t)q + 1];
-            sk[u] = SK[q];
-        }
-        for (int u = 0; u < 3; u++) {
-            if (kk[u] >= M) break;
-            const uint32_t k = kk[u];
-            const float Vs = (sk[u] >> 1) == KIND_WALL_OUTER ? 0.0f : vq[u];
-            SA[k] = make_float4((float)(((px[u][0] + F.shift[sl[u]][0]) - F.origin[0]) * ih),
-                                (float)(((px[u][1] + F.shift[sl[u]][1]) - F.origin[1]) * ih),
-                                (float)(((px[u][2] + F.shift[sl[u]][2]) - F.origin[2]) * ih), Vs);
-            SP[k] = Vs * pq[u];
-        }
-    }
+    double px[3][3];
+    float vq[3], pq[3];
+    uint8_t sk[3];
+    stage_spread(F, M, [&](int u, uint32_t q) {
+        for (int a = 0; a < 3; a++) px[u][a] = X[(size_t)a * N + q];
+        vq[u] = AUX[4 * (size_t)q];
+        pq[u] = RP[2 * (size_t)q + 1];
+        sk[u] = SK[q];
+    }, [&](int u, uint32_t k, int sl) {
+        const float Vs = (sk[u] >> 1) == KIND_WALL_OUTER ? 0.0f : vq[u];
+        SA[k] = make_float4((float)(((px[u][0] + F.shift[sl][0]) - F.origin[0]) * ih),
+                            (float)(((px[u][1] + F.shift[sl][1]) - F.origin[1]) * ih),
+                            (float)(((px[u][2] + F.shift[sl][2]) - F.origin[2]) * ih), Vs);
+        SP[k] = Vs * pq[u];
+    });
 }
 
 // Pressure filter over the brick sweeps' neighbour masks (the density sweep's, replayed as
