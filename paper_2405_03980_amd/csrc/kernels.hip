@@ -807,6 +807,9 @@ __global__ void k_collide_apply(DevState s, int flagged)
 constexpr int kBrickThreads = 512;
 constexpr int kStageDensity = 2048;
 constexpr int kStageForce = 1408;
+// The force sweep and the pressure filter replay masks only for bricks the density sweep
+// could stage: a brick too large for the density stage must be too large for theirs.
+static_assert(kStageForce <= kStageDensity, "mask replay needs the density sweep's masks");
 
 struct BrickFrame {
     uint32_t begin[64];   // sorted index of each slot's first particle
