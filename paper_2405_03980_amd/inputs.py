@@ -61,13 +61,16 @@ class Workload:
 def base_params(kernel: int, geometry: int, dx: float, lo, hi, c0: float,
                 *, h_factor: float = 1.3, rho0: float = 1.0, nu: float = 1.0 / 88.6,
                 sigma_frac: float = 0.05, C_l: float = 0.01, kappa_I: float = 0.4,
-                cell_factor: int = 1) -> dict:
+                cell_factor: int = 1, pressure_filter: int = 0, coll_alpha: float = 0.0,
+                coll_e: float = 0.0) -> dict:
     """Coefficient set of the synthetic workloads.
 
     nu = 1/88.6 is the non-dimensional kinematic viscosity matching the paper's
     rotation Reynolds number (Sec. 3: eta_n = 0.566 kappa rho_n, Omega = 5 rad/s,
     R = 0.1 cm); the interfacial coefficient is a fixed fraction of the Tait
     stiffness rho0 c0^2 / 7 and the mutual-friction coefficient a small constant.
+    pressure_filter, coll_alpha and coll_e switch on Algorithm 1's pressure filter and
+    collision step (off by default, as in the benchmarked step).
     """
     gamma = 7.0
     return dict(
@@ -76,6 +79,7 @@ def base_params(kernel: int, geometry: int, dx: float, lo, hi, c0: float,
         rho0=float(rho0), c0=float(c0), gamma=gamma, mass=[0.0, 0.0],
         eta=float(nu * rho0), sigma_T=float(sigma_frac * rho0 * c0 * c0 / gamma),
         C_l=float(C_l * rho0), kappa_I=float(kappa_I), cell_factor=int(cell_factor),
+        pressure_filter=int(pressure_filter), coll_alpha=float(coll_alpha), coll_e=float(coll_e),
     )
 
 
