@@ -11,6 +11,7 @@ import math
 
 import numpy as np
 import pytest
+from scipy import integrate
 
 from oracle import oracle as O
 from paper_2405_03980_amd import inputs as I
@@ -53,6 +54,23 @@ def test_filter_keeps_a_linear_field_on_a_lattice():
     Pf = O.pressure_filter(w.params, w.x, w.species, w.kind, rho, P)
     assert inner.sum() > 1000
     assert np.abs(Pf[inner] - P[inner]).max() < 1e-13
+
+
+def test_filter_is_the_kernel_smoothing_in_the_limit():
+    """At fixed h with dx -> 0 the lattice average tends to the kernel convolution, which
+    multiplies cos(kx) by the kernel's Fourier transform 4 pi int W(r) sin(kr)/(kr) r^2 dr
+    (by quadrature); the self weight is part of that lattice sum."""
+    h, k = 0.125, 2 * math.pi
+    what, _ = integrate.quad(lambda r: 4 * math.pi * r * r * O.W(I.KERNEL_WENDLAND_C2, h, r)
+                             * math.sin(k * r) / (k * r), 0, 2 * h, epsabs=1e-14, epsrel=1e-13,
+                             limit=200)
+    errs = []
+    for n in (16, 32):
+        w = I.make_box(n, kernel=I.KERNEL_WENDLAND_C2, rigid=False, noise=0.0, h_factor=h * n)
+        e = 0.1 * np.cos(k * w.x[0])
+        Pf = O.pressure_filter(w.params, w.x, w.species, w.kind, np.ones(w.n), 1.0 + e)
+        errs.append(abs(float(np.dot(Pf - 1.0, e) / np.dot(e, e)) - what))
+    assert errs[1] < errs[0] and errs[1] < 5e-6, errs
 
 
 def _W_wendland(h, r):
