@@ -1985,23 +1985,41 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t value, size_t n)
 // times the largest are on; 8-connected sets of on pixels are labelled by their smallest
 // pixel index; components of at least min_pixels pixels are counted.
 
-// One thread per particle; threads of particles outside the section leave at once.
+// Deposits intensity I of the particle at (x0, x1) into its pixel: non-negative doubles
+// order like their bit patterns, so the largest wins through an integer atomicMax.
+__device__ __forceinline__ uint32_t vortex_deposit(const VortexArgs &a, double x0, double x1,
+                                                   double I, unsigned long long *img)
+{
+    if (!isfinite(I)) return ERR_NONFINITE;
+    int ix = (int)floor((x0 - a.lox) / a.dx), iy = (int)floor((x1 - a.loy) / a.dx);
+    ix = min(max(ix, 0), a.nx - 1);
+    iy = min(max(iy, 0), a.ny - 1);
+    atomicMax(&img[(size_t)iy * a.nx + ix], (unsigned long long)__double_as_longlong(I));
+    return 0u;
+}
+
+// Whether z lies in the section -dx <= z - z0 < dx (z periodic with period Lz).
+__device__ __forceinline__ bool in_section(const VortexArgs &a, double z)
+{
+    double dz = z - a.z0;
+    dz = dz - a.Lz * floor(dz / a.Lz + 0.5);
+    return dz >= -a.dx && dz < a.dx;
+}
+
+// Intensity of fluid particle p of the section, walking its cell stencil in FP64.
 template <typename R>
-__global__ void k_vortex_intensity(DevState s, VortexArgs a, unsigned long long *img)
+__device__ __forceinline__ uint32_t vortex_one(const DevState &s, const InstDesc *d,
+                                               const VortexArgs &a, uint32_t p,
+                                               unsigned long long *img)
 {
 #pragma clang fp contract(off)
-    PIdx t = map_thread(s);
-    if (!t.active) return;
-    const InstDesc *d = t.d;
-    const uint32_t p = t.p, N = s.N;
+    const uint32_t N = s.N;
     const int cur = s.cur;
     const double *X = s.x[cur], *Wv = s.w[cur];
     const uint8_t *SK = s.sk[cur];
-    if ((SK[p] >> 1) != KIND_FLUID) return;
+    if ((SK[p] >> 1) != KIND_FLUID) return 0u;
     const double xi0 = X[p], xi1 = X[N + p], xi2 = X[2 * N + p];
-    double dz = xi2 - a.z0;
-    dz = dz - a.Lz * floor(dz / a.Lz + 0.5);
-    if (!(dz >= -a.dx && dz < a.dx)) return;
+    if (!in_section(a, xi2)) return 0u;
     // spins at the end of the step: the closing half kick is still pending for fluid
     // particles (as in k_read); walls hold their exact spin
     const R *AL = (const R *)s.alpha;
@@ -2032,16 +2050,150 @@ __global__ void k_vortex_intensity(DevState s, VortexArgs a, unsigned long long 
             s2 += g * (w0 * r1 - w1 * r0);
         }
     });
-    const double I = sqrt(s0 * s0 + s1 * s1 + s2 * s2);
-    if (!isfinite(I)) err |= ERR_NONFINITE;
-    int ix = (int)floor((xi0 - a.lox) / a.dx), iy = (int)floor((xi1 - a.loy) / a.dx);
-    ix = min(max(ix, 0), a.nx - 1);
-    iy = min(max(iy, 0), a.ny - 1);
-    if (isfinite(I)) {
-        // non-negative doubles order like their bit patterns
-        const unsigned long long bits = (unsigned long long)__double_as_longlong(I);
-        atomicMax(&img[(size_t)iy * a.nx + ix], bits);
+    return err | vortex_deposit(a, xi0, xi1, sqrt(s0 * s0 + s1 * s1 + s2 * s2), img);
+}
+
+// One thread per particle; threads of particles outside the section leave at once.
+template <typename R>
+__global__ void k_vortex_intensity(DevState s, VortexArgs a, unsigned long long *img)
+{
+    PIdx t = map_thread(s);
+    if (!t.active) return;
+    const uint32_t err = vortex_one<R>(s, t.d, a, t.p, img);
+    if (err) atomicOr(s.err, err);
+}
+
+// Stages what the brick intensity reads of the neighbourhood: position relative to the
+// brick centre in units of h with V = m/rho for a viscous particle (0 otherwise, so that
+// the others drop out of the sum), and the spin at the end of the step.
+__device__ __forceinline__ void stage_vortex(const DevState &s, const InstDesc *d, const BrickFrame &F,
+                                             uint32_t M, double pend, float4 *SA, float4 *SW)
+{
+    const uint32_t N = s.N;
+    const int cur = s.cur;
+    const double *X = s.x[cur], *Wv = s.w[cur];
+    const uint8_t *SK = s.sk[cur];
+    const float *AL = (const float *)s.alpha;
+    const float *RP = (const float *)s.rhoP;
+    const double ih = d->inv_h, m1 = d->mass[1];
+    double px[3][3], pw[3][3];
+    float al[3][3], rq[3];
+    uint8_t sk[3];
+    stage_spread(F, M, [&](int u, uint32_t q) {
+        for (int c = 0; c < 3; c++) {
+            px[u][c] = X[(size_t)c * N + q];
+            pw[u][c] = Wv[(size_t)c * N + q];
+            al[u][c] = AL[(size_t)c * N + q];
+        }
+        rq[u] = RP[2 * (size_t)q];
+        sk[u] = SK[q];
+    }, [&](int u, uint32_t k, int sl) {
+        const double pk = (sk[u] >> 1) == KIND_FLUID ? pend : 0.0;
+        SA[k] = make_float4((float)(((px[u][0] + F.shift[sl][0]) - F.origin[0]) * ih),
+                            (float)(((px[u][1] + F.shift[sl][1]) - F.origin[1]) * ih),
+                            (float)(((px[u][2] + F.shift[sl][2]) - F.origin[2]) * ih),
+                            (sk[u] & 1) ? (float)(m1 / (double)rq[u]) : 0.0f);
+        SW[k] = make_float4((float)__fma_rn(pk, (double)al[u][0], pw[u][0]),
+                            (float)__fma_rn(pk, (double)al[u][1], pw[u][1]),
+                            (float)__fma_rn(pk, (double)al[u][2], pw[u][2]), 0.0f);
+    });
+}
+
+// Intensity over the brick sweeps' neighbour masks (FP32-mixed path; the density sweep of
+// the same positions stored them): one workgroup per brick whose cells reach the section,
+// lanes = (target, group g of G) over the cell's fluid particles in the section.  With
+// r_ij = h r_s and F_ij = (wnorm cF / h^2) Fhat, each term is V_j Fhat (w_i + w_j) x r_s
+// (compensated FP32 sums) times 2 eta wnorm cF / h (FP64).  Bricks too large to stage, and
+// stencils too long for the masks, use the per-particle walk.
+__global__ void __launch_bounds__(kBrickThreads, 4) k_vortex_cand(DevState s, VortexArgs a,
+                                                                unsigned long long *img)
+{
+    __shared__ BrickFrame F;
+    __shared__ float4 SA[kStageForce];  // position (brick frame), V of a viscous particle
+    __shared__ float4 SW[kStageForce];  // spin at the end of the step
+    __shared__ int16_t tbl[kBrickThreads / 64][kCandWin][64];
+    const uint32_t brick = brick_of_workgroup(blockIdx.x, gridDim.x);
+    const uint32_t bxyz = s.brick_xyz[brick];
+    const InstDesc *d = s.desc + s.brick_inst[brick];
+    {
+        // the brick's two cell layers span [zc - e, zc + e): leave unless the section is near
+        const double e = d->edge[2];
+        double dz = d->lo[2] + (double)(2 * (int)(bxyz >> 20) + 1) * e - a.z0;
+        dz = dz - a.Lz * floor(dz / a.Lz + 0.5);
+        if (!(fabs(dz) < e + a.dx + 1e-6 * e)) return;  // the same for the whole workgroup
     }
+    const uint32_t N = s.N;
+    const double *X = s.x[s.cur];
+    const uint8_t *SK = s.sk[s.cur];
+    const uint32_t M = brick_frame(s, d, brick, bxyz, F, kStageForce);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int ts[3];
+    const bool has_cell = brick_target(d, bxyz, w, ts);
+    const int tslot = slot_index(ts[0], ts[1], ts[2]);
+    uint32_t err = 0;
+    if (!F.ok) {
+        if (has_cell) {
+            const uint32_t nt = F.off[tslot + 1] - F.off[tslot];
+            for (uint32_t i = lane; i < nt; i += 64) err |= vortex_one<float>(s, d, a, F.begin[tslot] + i, img);
+        }
+        if (err) atomicOr(s.err, err);
+        return;
+    }
+    stage_vortex(s, d, F, M, a.pend, SA, SW);
+    __syncthreads();
+    if (!has_cell) return;
+    const uint32_t toff = F.off[tslot], pbase = F.begin[tslot];
+    const uint32_t nt = F.off[tslot + 1] - toff;
+    if (nt == 0) return;
+    const StencilList S = stencil_list(F, ts, lane, &tbl[w][0][0]);
+    if (S.NW > (uint32_t)kCandWin) {
+        for (uint32_t i = lane; i < nt; i += 64) err |= vortex_one<float>(s, d, a, pbase + i, img);
+        if (err) atomicOr(s.err, err);
+        return;
+    }
+    const int NW = (int)S.NW;
+    const double kv = 2.0 * d->eta * d->wnorm * (d->kernel == KERNEL_WENDLAND ? 5.0 : 1.0) * d->inv_h;
+    auto sweep = [&](auto kt) {
+        constexpr int KT = decltype(kt)::value;
+        for (uint32_t t0 = 0; t0 < nt; t0 += 64) {
+            const uint32_t nb = min(64u, nt - t0);
+            bool tgt = false;
+            if ((uint32_t)lane < nb) {
+                const uint32_t q = pbase + t0 + lane;
+                tgt = (SK[q] >> 1) == KIND_FLUID && in_section(a, X[2 * (size_t)N + q]);
+            }
+            const uint64_t Mt = __ballot(tgt);
+            if (Mt == 0) continue;
+            const int n = __popcll(Mt);
+            const int G = 64 / n;
+            const int g = lane / n;
+            const bool target = g < G;
+            const uint32_t t = (uint32_t)__builtin_ctzll(drop_low_bits(Mt, (uint32_t)(lane % n)));
+            const uint32_t p = pbase + t0 + t;
+            const float4 Ai = SA[toff + t0 + t], Wi = SW[toff + t0 + t];
+            HitReplay hr(s.masks + (size_t)p * kMaskSlots, NW, target, g, G);
+            Acc<float, true> s0, s1, s2;
+            for (uint32_t i = 0; i < hr.cnt; i++) {
+                const uint32_t k = hr.next(tbl[w]);
+                const float4 A = SA[k], Wj = SW[k];
+                const float r0 = Ai.x - A.x, r1 = Ai.y - A.y, r2 = Ai.z - A.z;
+                float Wk, Fh;
+                shape_WF<KT>(r0 * r0 + r1 * r1 + r2 * r2, Wk, Fh);
+                const float gv = A.w * Fh;
+                const float w0 = Wi.x + Wj.x, w1 = Wi.y + Wj.y, w2 = Wi.z + Wj.z;
+                s0.add(gv * (w1 * r2 - w2 * r1));
+                s1.add(gv * (w2 * r0 - w0 * r2));
+                s2.add(gv * (w0 * r1 - w1 * r0));
+            }
+            const double v0 = group_total(s0.s, s0.c, lane, n, G);
+            const double v1 = group_total(s1.s, s1.c, lane, n, G);
+            const double v2 = group_total(s2.s, s2.c, lane, n, G);
+            if (target && g == 0)
+                err |= vortex_deposit(a, X[p], X[(size_t)N + p], kv * sqrt(v0 * v0 + v1 * v1 + v2 * v2), img);
+        }
+    };
+    if (d->kernel == KERNEL_WENDLAND) sweep(std::integral_constant<int, KERNEL_WENDLAND>());
+    else sweep(std::integral_constant<int, KERNEL_CUBIC>());
     if (err) atomicOr(s.err, err);
 }
 
@@ -2237,11 +2389,12 @@ hipError_t launch_debug_nbr(const DevState &d, const Launch &L, hipStream_t st, 
 }
 
 hipError_t launch_vortex_intensity(const DevState &d, const Launch &L, hipStream_t st,
-                                   const VortexArgs &a, unsigned long long *img,
+                                   const VortexArgs &a, bool masks, unsigned long long *img,
                                    unsigned long long *vmax)
 {
     const unsigned g = grid_for(d.n_waves, L.bs_stream);
     if (d.precision == 0) k_vortex_intensity<double><<<g, L.bs_stream, 0, st>>>(d, a, img);
+    else if (masks) k_vortex_cand<<<d.n_bricks, kBrickThreads, 0, st>>>(d, a, img);
     else k_vortex_intensity<float><<<g, L.bs_stream, 0, st>>>(d, a, img);
     k_vortex_max<<<1, 1024, 0, st>>>(img, (uint32_t)(a.nx * a.ny), vmax);
     return hipGetLastError();

@@ -360,6 +360,8 @@ struct sph_batch {
     std::vector<sph_params> params;  // as given at creation
     std::vector<StepParams> steptab;
     bool loaded = false;
+    bool masks_current = false;  // the last density launch was the brick sweep (its masks
+                                 // hold the neighbours of the current positions)
     double pending_dt = 0.0;  // closing half kick of this dt still to apply
     bool use_graph = true;
     GraphCache graphs[2];
@@ -425,6 +427,7 @@ sph_status enqueue_step(sph_batch *b, int mode, double kick, double dt)
     d.cur ^= 1;
     if ((s = prof_mark(b, SPH_K_DENSITY)) != SPH_OK) return s;
     if ((s = check_launch(b, launch_density(d, b->L, st), "density")) != SPH_OK) return s;
+    b->masks_current = d.precision != 0 && b->L.sweep == SWEEP_CAND && d.n_bricks != 0;
     if (d.any_filter) {
         if ((s = prof_mark(b, SPH_K_FILTER)) != SPH_OK) return s;
         if ((s = check_launch(b, launch_filter(d, b->L, st), "pressure filter")) != SPH_OK) return s;
@@ -946,7 +949,7 @@ sph_status sph_vortex_image(sph_sim *s, double z0, double theta, int32_t min_pix
     unsigned long long *img = (unsigned long long *)image;
     hipError_t e = launch_fill_u32((uint32_t *)image, 0u, 2 * (size_t)n, b->stream);
     if (e == hipSuccess) e = launch_fill_u32((uint32_t *)scratch, 0u, ((n + 3) & ~1u) + 2, b->stream);
-    if (e == hipSuccess) e = launch_vortex_intensity(b->ds, b->L, b->stream, a, img, vmax);
+    if (e == hipSuccess) e = launch_vortex_intensity(b->ds, b->L, b->stream, a, b->masks_current, img, vmax);
     if (e == hipSuccess) e = launch_vortex_label_init(b->stream, img, vmax, theta, n, labels);
     if (e != hipSuccess) return hip_fail(e, b->err, "vortex image");
     // Relax until a pass changes nothing.  Each pass carries a component's smallest label

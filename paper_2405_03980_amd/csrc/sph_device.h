@@ -130,8 +130,10 @@ struct VortexArgs {
     double z0, Lz, dx, lox, loy, pend;
     int32_t nx, ny;
 };
+// masks: the brick density sweep's masks hold the neighbours of the current positions
+// (FP32-mixed path), so the brick intensity kernel may replay them.
 hipError_t launch_vortex_intensity(const DevState &d, const Launch &L, hipStream_t st,
-                                   const VortexArgs &a, unsigned long long *img,
+                                   const VortexArgs &a, bool masks, unsigned long long *img,
                                    unsigned long long *vmax);
 hipError_t launch_vortex_label_init(hipStream_t st, const unsigned long long *img,
                                     const unsigned long long *vmax, double theta, uint32_t n,

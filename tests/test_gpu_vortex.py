@@ -77,6 +77,46 @@ def test_vortex_image_after_steps():
     _compare(got, oimg, olab, oc, 0.4, 3, 1e-11)
 
 
+@pytest.mark.parametrize("sweep", [3, 1])
+def test_mixed_vortex_image_after_steps(sweep):
+    """FP32-mixed after steps with rotating walls: the brick intensity (sweep 3, replaying
+    the density sweep's masks of the stepped positions) and the per-particle one (sweep 1)
+    against the oracle's state, within 1e-5."""
+    from paper_2405_03980_amd import sim as S
+    w = _cylinder(20, 9)
+    s = S.Simulation(w.params, w.n, precision=MIXED)
+    s.set_tuning(sweep=sweep)
+    s.init(w.x, w.v, w.omega, w.species, w.kind)
+    s.step(1e-4, w.Omega, 4)
+    got = s.vortex_image(0.2, 0.4, 2)
+    s.close()
+    ref = O.State.from_workload(w)
+    ref.step(1e-4, w.Omega, 4)
+    oc, oimg, olab = V.vortex_image(w.params, ref.x, ref.omega, w.species, w.kind, ref.rho, 0.2,
+                                    0.4, 2)
+    _compare(got, oimg, olab, oc, 0.4, 2, 1e-5)
+
+
+def test_vortex_image_after_a_sweep_change():
+    """Stepping with the brick sweeps, then switching to the per-particle ones and stepping
+    again: the image follows the oracle (the stored masks, now of older positions, are not
+    replayed)."""
+    from paper_2405_03980_amd import sim as S
+    w = _cylinder(18, 10)
+    s = S.Simulation(w.params, w.n, precision=MIXED)
+    s.init(w.x, w.v, w.omega, w.species, w.kind)
+    s.step(1e-4, w.Omega, 2)
+    s.set_tuning(sweep=1)
+    s.step(1e-4, w.Omega, 1)
+    got = s.vortex_image(0.0, 0.5, 1)
+    s.close()
+    ref = O.State.from_workload(w)
+    ref.step(1e-4, w.Omega, 3)
+    oc, oimg, olab = V.vortex_image(w.params, ref.x, ref.omega, w.species, w.kind, ref.rho, 0.0,
+                                    0.5, 1)
+    _compare(got, oimg, olab, oc, 0.5, 1, 1e-5)
+
+
 def test_vortex_image_is_reproducible():
     w = _cylinder(20, 7)
     s = _sim(w, MIXED)
