@@ -706,29 +706,48 @@ __global__ void k_filter(DevState s)
     if (err) atomicOr(s.err, err);
 }
 
-// Collision step (Algorithm 1), FP64 on both paths, one thread per fluid particle of the
+// Collision step (Algorithm 1), decided and computed in FP64 on both paths, for the
 // instances that have it on.  A fluid particle i closer than rc to a neighbour j that it
 // approaches ((v_i - v_j).(x_i - x_j) < 0) takes
 //   dv_i = -(1 + e) mu (v_ij . r_ij) / |r_ij|^2 r_ij,  mu = m_j / (m_i + m_j), 1 for walls,
 // summed over all such neighbours from the velocities before the step; the new velocities
 // go to the other velocity buffer (free between the reorder and the next step's) and
-// k_collide_apply copies them back.  Only cells within rc of the particle are walked
-// (rc < 2h; the test on each axis keeps a margin, so pruning never drops a pair).  With
-// `flagged`, only the particles the brick density sweep flagged as having a neighbour near
-// rc are tested (the others cannot collide).  Neither the density nor the pressure filter
-// reads velocities, so the step may run after them.
-__global__ void k_collide(DevState s, int flagged)
+// k_collide_apply copies them back.  Neither the density nor the pressure filter reads
+// velocities, so the step may run after them.  A particle takes either the near
+// neighbours the brick density sweep listed for it, or a walk over the cells within rc
+// (rc < 2h; the test on each axis keeps a margin, so pruning never drops a pair).
+
+// Impulse on fluid particle i (mass mi, velocity vi) from neighbour q at r = x_i - x_q
+// (minimum image, r2 = |r|^2 < rc^2), added to dv when the pair approaches.
+__device__ __forceinline__ void collide_term(const InstDesc *d, double mi, const double vi[3],
+                                             const double *Vv, uint32_t N, uint32_t q,
+                                             uint8_t skq, double r0, double r1, double r2,
+                                             double rr, double dv[3])
 {
-    PIdx t = map_thread(s);
-    if (!t.active) return;
-    const InstDesc *d = t.d;
-    if (!d->coll) return;
-    const uint32_t N = s.N, p = t.p;
-    if (flagged && !s.cflag[p]) return;
+    double vn;
+    {
+#pragma clang fp contract(off)
+        vn = (vi[0] - Vv[q]) * r0;
+        vn = vn + (vi[1] - Vv[N + q]) * r1;
+        vn = vn + (vi[2] - Vv[2 * N + q]) * r2;
+    }
+    if (!(vn < 0.0)) return;
+    const double mu = (skq >> 1) == KIND_FLUID ? d->mass[skq & 1] / (mi + d->mass[skq & 1]) : 1.0;
+    const double g = -d->coll_e1 * mu * vn / rr;
+    dv[0] += g * r0;
+    dv[1] += g * r1;
+    dv[2] += g * r2;
+}
+
+// The collision step of fluid particle p, walking the cells within rc; writes its new
+// velocity to the other velocity buffer.
+__device__ __forceinline__ uint32_t collide_one(const DevState &s, const InstDesc *d, uint32_t p)
+{
+    const uint32_t N = s.N;
     const int cur = s.cur;
     const uint8_t *SK = s.sk[cur];
     const uint8_t ski = SK[p];
-    if ((ski >> 1) != KIND_FLUID) return;
+    if ((ski >> 1) != KIND_FLUID) return 0u;
     const double *X = s.x[cur], *Vv = s.v[cur];
     double *VN = s.v[cur ^ 1];
     const double xi[3] = {X[p], X[N + p], X[2 * N + p]};
@@ -748,8 +767,7 @@ __global__ void k_collide(DevState s, int flagged)
             if (above + (double)(o - 1) * e < reach) ohi[a] = o;
         }
     }
-    const double mi = d->mass[ski & 1];
-    const double rc2 = d->coll_rc2, e1 = d->coll_e1;
+    const double mi = d->mass[ski & 1], rc2 = d->coll_rc2;
     uint32_t err = 0;
     double dv[3] = {0.0, 0.0, 0.0};
     for_cells_in(s, d, c[0], c[1], c[2], olo, ohi, err, [&](uint32_t b, uint32_t e) {
@@ -757,23 +775,9 @@ __global__ void k_collide(DevState s, int flagged)
             if (q == p) continue;
             const double r0 = min_img(d, 0, xi[0] - X[q]);
             const double r1 = min_img(d, 1, xi[1] - X[N + q]);
-            const double rr2 = min_img(d, 2, xi[2] - X[2 * N + q]);
-            const double d2 = r2_exact(r0, r1, rr2);
-            if (!(d2 < rc2)) continue;
-            double vn;
-            {
-#pragma clang fp contract(off)
-                vn = (vi[0] - Vv[q]) * r0;
-                vn = vn + (vi[1] - Vv[N + q]) * r1;
-                vn = vn + (vi[2] - Vv[2 * N + q]) * rr2;
-            }
-            if (!(vn < 0.0)) continue;
-            const uint8_t skq = SK[q];
-            const double mu = (skq >> 1) == KIND_FLUID ? d->mass[skq & 1] / (mi + d->mass[skq & 1]) : 1.0;
-            const double g = -e1 * mu * vn / d2;
-            dv[0] += g * r0;
-            dv[1] += g * r1;
-            dv[2] += g * rr2;
+            const double r2 = min_img(d, 2, xi[2] - X[2 * N + q]);
+            const double rr = r2_exact(r0, r1, r2);
+            if (rr < rc2) collide_term(d, mi, vi, Vv, N, q, SK[q], r0, r1, r2, rr, dv);
         }
     });
     for (int a = 0; a < 3; a++) {
@@ -781,16 +785,69 @@ __global__ void k_collide(DevState s, int flagged)
         VN[(size_t)a * N + p] = vnew;
         if (!isfinite(vnew)) err |= ERR_NONFINITE;
     }
+    return err;
+}
+
+// The collision step of fluid particle p over the near neighbours the brick density sweep
+// listed for it (n of them, in sorted-index order so that the sum does not depend on the
+// order the lanes listed them).
+__device__ __forceinline__ uint32_t collide_listed(const DevState &s, const InstDesc *d, uint32_t p,
+                                                   uint32_t n)
+{
+    const uint32_t N = s.N;
+    const int cur = s.cur;
+    const uint8_t *SK = s.sk[cur];
+    const uint8_t ski = SK[p];
+    if ((ski >> 1) != KIND_FLUID) return 0u;
+    const double *X = s.x[cur], *Vv = s.v[cur];
+    double *VN = s.v[cur ^ 1];
+    uint32_t q[kNearCap];
+    for (uint32_t a = 0; a < n; a++) {
+        uint32_t v = s.nearq[(size_t)p * kNearCap + a], b = a;
+        for (; b > 0 && q[b - 1] > v; b--) q[b] = q[b - 1];
+        q[b] = v;
+    }
+    const double xi[3] = {X[p], X[N + p], X[2 * N + p]};
+    const double vi[3] = {Vv[p], Vv[N + p], Vv[2 * N + p]};
+    const double mi = d->mass[ski & 1], rc2 = d->coll_rc2;
+    double dv[3] = {0.0, 0.0, 0.0};
+    for (uint32_t a = 0; a < n; a++) {
+        const uint32_t j = q[a];
+        const double r0 = min_img(d, 0, xi[0] - X[j]);
+        const double r1 = min_img(d, 1, xi[1] - X[N + j]);
+        const double r2 = min_img(d, 2, xi[2] - X[2 * N + j]);
+        const double rr = r2_exact(r0, r1, r2);
+        if (rr < rc2) collide_term(d, mi, vi, Vv, N, j, SK[j], r0, r1, r2, rr, dv);
+    }
+    uint32_t err = 0;
+    for (int a = 0; a < 3; a++) {
+        const double vnew = vi[a] + dv[a];
+        VN[(size_t)a * N + p] = vnew;
+        if (!isfinite(vnew)) err |= ERR_NONFINITE;
+    }
+    return err;
+}
+
+// listed: the brick density sweep of this step left cflag = number of listed near
+// neighbours (0: none, kNearOverflow: more than kNearCap, or not listed: walk the cells).
+__global__ void k_collide(DevState s, int listed)
+{
+    PIdx t = map_thread(s);
+    if (!t.active || !t.d->coll) return;
+    const uint32_t f = listed ? s.cflag[t.p] : (uint32_t)kNearOverflow;
+    if (f == 0) return;
+    const uint32_t err = f == (uint32_t)kNearOverflow ? collide_one(s, t.d, t.p)
+                                                      : collide_listed(s, t.d, t.p, f);
     if (err) atomicOr(s.err, err);
 }
 
-__global__ void k_collide_apply(DevState s, int flagged)
+__global__ void k_collide_apply(DevState s, int listed)
 {
     PIdx t = map_thread(s);
     if (!t.active || !t.d->coll) return;
     const uint32_t N = s.N, p = t.p;
     const int cur = s.cur;
-    if ((flagged && !s.cflag[p]) || (s.sk[cur][p] >> 1) != KIND_FLUID) return;
+    if ((listed && !s.cflag[p]) || (s.sk[cur][p] >> 1) != KIND_FLUID) return;
     for (int a = 0; a < 3; a++) s.v[cur][(size_t)a * N + p] = s.v[cur ^ 1][(size_t)a * N + p];
 }
 
@@ -938,11 +995,11 @@ __device__ __forceinline__ bool brick_target(const InstDesc *d, uint32_t bxyz, i
 }
 
 
-// Sum of the G partial (Kahan) sums of a target, held by lanes t, t + ntc, ... (t < ntc):
-// a tree over the groups in a fixed order, in FP64; the total is valid on lane t.
-__device__ __forceinline__ double group_total(float s_, float c_, int lane, int ntc, int G)
+// Sum of the G partial sums of a target, held by lanes t, t + ntc, ... (t < ntc): a tree
+// over the groups in a fixed order, in FP64; the total is valid on lane t.  group_total
+// takes a Kahan pair.
+__device__ __forceinline__ double group_total_d(double v, int lane, int ntc, int G)
 {
-    double v = (double)s_ - (double)c_;
     const int g = lane / ntc;
     for (int off = 1; off < G; off <<= 1) {
         const int src = lane + off * ntc;
@@ -950,6 +1007,11 @@ __device__ __forceinline__ double group_total(float s_, float c_, int lane, int 
         if ((g & (2 * off - 1)) == 0 && g + off < G) v += o;
     }
     return v;
+}
+
+__device__ __forceinline__ double group_total(float s_, float c_, int lane, int ntc, int G)
+{
+    return group_total_d((double)s_ - (double)c_, lane, ntc, G);
 }
 
 // Clears the k lowest set bits of m (k < popcount(m)): a binary search for the position of
@@ -1372,10 +1434,12 @@ __device__ __forceinline__ void test_targets(const float4 *stage, const float *p
     }
 }
 
-// With COLL, the sweep also flags (cflag) every target that has a neighbour within the
-// collision distance (plus a relative margin of 1e-4 on its square, far above the FP32
-// rounding of the staged distances), so that the collision step tests only those exactly.
-// Targets evaluated per particle (fallbacks) are flagged unconditionally.
+// With COLL, the sweep also lists, per target, the neighbours within the collision distance
+// (plus a relative margin of 1e-4 on its square, far above the FP32 rounding of the staged
+// distances): up to kNearCap sorted indices in nearq and their number in cflag, so that
+// the collision step tests only those, exactly.  Targets with more, targets evaluated per
+// particle (fallbacks) and collision distances near 2h get kNearOverflow: the collision
+// step walks their cells.
 template <bool KAHAN, bool COLL>
 __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
 {
@@ -1383,6 +1447,9 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
     __shared__ float4 stage[kStageDensity];
     __shared__ int16_t tbl[kBrickThreads / 64][kCandWin][64];
     __shared__ uint64_t msk[kBrickThreads / 64][kListTargets][kCandWin];
+    __shared__ uint32_t ncnt[kBrickThreads / 64][kListTargets];  // near neighbours listed (COLL)
+    __shared__ int16_t nearl[kBrickThreads][kNearCap + 1];        // a lane's near hits (COLL;
+                                                                  // the last is a spare)
     const uint32_t brick = brick_of_workgroup(blockIdx.x, gridDim.x);
     const uint32_t bxyz = s.brick_xyz[brick];
     const InstDesc *d = s.desc + s.brick_inst[brick];
@@ -1398,7 +1465,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
             const uint32_t nt = F.off[tslot + 1] - F.off[tslot];
             for (uint32_t i = lane; i < nt; i += 64) {
                 err |= density_one<float, KAHAN>(s, d, F.begin[tslot] + i);
-                if (COLL) s.cflag[F.begin[tslot] + i] = 1;
+                if (COLL) s.cflag[F.begin[tslot] + i] = kNearOverflow;
             }
         }
         if (err) atomicOr(s.err, err);
@@ -1415,7 +1482,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
     if (S.NW > (uint32_t)kCandWin) {
         for (uint32_t i = lane; i < nt; i += 64) {
             err |= density_one<float, KAHAN>(s, d, pbase + i);
-            if (COLL) s.cflag[pbase + i] = 1;
+            if (COLL) s.cflag[pbase + i] = kNearOverflow;
         }
         if (err) atomicOr(s.err, err);
         return;
@@ -1435,6 +1502,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
     }
     const float cut2 = (float)(d->cut2 * d->inv_h * d->inv_h);  // positions in units of h
     const float rc2m = (float)(d->coll_rc2 * d->inv_h * d->inv_h * (1.0 + 1e-4));
+    const bool list_ok = d->coll_rc2 < 0.9 * d->cut2;  // well inside the masks' reach
     const int kernel = d->kernel;
     // compiled once per smoothing kernel, chosen per brick (as in the force sweep)
     auto sweep = [&](auto kt) {
@@ -1468,6 +1536,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
                     if ((vs >> 6) == (uint32_t)c) mw[c] &= keep;
             }
             if ((uint32_t)lane < ntc) {
+                if (COLL) ncnt[w][lane] = 0u;
                 uint64_t *gm = s.masks + (size_t)(pbase + t0 + lane) * kMaskSlots;
 #pragma unroll
                 for (int c = 0; c < kCandWin; c++) {
@@ -1491,24 +1560,40 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
             hit_share([&](int cc) { return mrow[cc]; }, act ? H : 0u, g, G, cnt, c, mc);
             const float4 me = stage[toff + t0 + tt];
             Acc<float, KAHAN> sw, su;
-            bool near = false;
-            auto next_hit = [&]() {
+            uint32_t nloc = 0;  // near hits of this lane (COLL)
+            auto next_k = [&]() {
                 while (mc == 0) mc = mrow[++c];
                 const int j = __builtin_ctzll(mc);
                 mc &= mc - 1;
-                return stage[tbl[w][c][j]];
+                return (uint32_t)tbl[w][c][j];
             };
             // a per-lane trip count (lanes leave as they finish), two hits per trip so that
             // the compensated sums alternate registers instead of being copied back each hit
 #pragma unroll 2
             for (uint32_t i = 0; i < cnt; i++) {
-                const float4 qc = next_hit();
+                const uint32_t kq = next_k();
+                const float4 qc = stage[kq];
                 const float d0 = me.x - qc.x, d1 = me.y - qc.y, d2 = me.z - qc.z;
                 const float r2s = d0 * d0 + d1 * d1 + d2 * d2;
                 const float W = shape_W<KT>(r2s);
                 sw.add(W);
                 su.add(qc.w != me.w ? W : 0.0f);
-                if (COLL) near |= r2s < rc2m;
+                if (COLL) {
+                    // branch-free: every hit is written to the next free slot (the spare once
+                    // the list is full), and only a near one advances the count
+                    nearl[threadIdx.x][min(nloc, (uint32_t)kNearCap)] = (int16_t)kq;
+                    nloc += r2s < rc2m ? 1u : 0u;
+                }
+            }
+            if (COLL && nloc) {
+                // after the loop: reserve the lane's slots of the target's list, then store
+                // their sorted indices
+                const uint32_t base = atomicAdd(&ncnt[w][tt], nloc);
+                for (uint32_t j = 0; j < nloc && j < (uint32_t)kNearCap && base + j < (uint32_t)kNearCap; j++) {
+                    const uint32_t kq = (uint32_t)nearl[threadIdx.x][j];
+                    const int sl = slot_of(F, kq);
+                    s.nearq[(size_t)(pbase + t0 + tt) * kNearCap + base + j] = F.begin[sl] + (kq - F.off[sl]);
+                }
             }
             const double SW = d->wnorm * group_total(sw.s, KAHAN ? sw.c : 0.0f, lane, (int)ntc, G);
             const double SU = d->wnorm * group_total(su.s, KAHAN ? su.c : 0.0f, lane, (int)ntc, G);
@@ -1518,11 +1603,12 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
                 err |= density_finish<float>(s, d, p, ski & 1, ski >> 1, SW, SU);
             }
             if (COLL) {
-                // a target is near if any of its G lanes (tt, tt + ntc, ...) saw a near hit
-                const uint64_t nbal = __ballot(near);
-                uint64_t rep = 0;
-                for (int k = 0; k < G; k++) rep |= 1ull << (k * (int)ntc);
-                if (act && g == 0) s.cflag[pbase + t0 + tt] = ((nbal >> tt) & rep) != 0 ? 1 : 0;
+                wave_lds_handoff();  // the counts of all of a target's lanes
+                if (act && g == 0) {
+                    const uint32_t nn = ncnt[w][tt];
+                    s.cflag[pbase + t0 + tt] =
+                        (uint8_t)(!list_ok || nn > (uint32_t)kNearCap ? (uint32_t)kNearOverflow : nn);
+                }
             }
             wave_lds_handoff();  // the masks are rewritten by the next round
         }
@@ -2340,10 +2426,10 @@ hipError_t launch_collide(const DevState &d, const Launch &L, hipStream_t st)
 {
     if (!d.any_coll) return hipSuccess;
     unsigned g = grid_for(d.n_waves, L.bs_stream);
-    // the brick density sweep (chosen as in launch_density) leaves the candidates flagged
-    const int flagged = (d.precision != 0 && L.sweep == SWEEP_CAND && d.n_bricks) ? 1 : 0;
-    k_collide<<<g, L.bs_stream, 0, st>>>(d, flagged);
-    k_collide_apply<<<g, L.bs_stream, 0, st>>>(d, flagged);
+    // the brick density sweep (chosen as in launch_density) lists the near neighbours
+    const int listed = (d.precision != 0 && L.sweep == SWEEP_CAND && d.n_bricks) ? 1 : 0;
+    k_collide<<<g, L.bs_stream, 0, st>>>(d, listed);
+    k_collide_apply<<<g, L.bs_stream, 0, st>>>(d, listed);
     return hipGetLastError();
 }
 

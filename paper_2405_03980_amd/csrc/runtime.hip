@@ -170,6 +170,7 @@ void carve(Carver &c, DevState &d, int n_inst, uint32_t N, uint32_t C, uint32_t 
     d.rhoP = c.take<char>(2 * (size_t)N * rs);
     d.pf = c.take<char>((filter ? (size_t)N : 1) * rs);
     d.cflag = c.take<uint8_t>(coll ? (size_t)N : 1);
+    d.nearq = c.take<uint32_t>(coll ? (size_t)N * kNearCap : 1);
     d.key = c.take<uint32_t>(N);
     d.slot = c.take<uint32_t>(N);
     d.tmp = c.take<uint32_t>(N);

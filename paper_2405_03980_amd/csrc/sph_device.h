@@ -63,7 +63,9 @@ struct DevState {
     void *aux;                    // [N][4]: V = m/rho, P/rho^2, 1/rho^2, V/S (0 if S = 0)
     void *rhoP;                   // [N][2]: rho, P (P before the pressure filter)
     void *pf;                     // [N]: filtered pressure (instances with the filter on)
-    uint8_t *cflag;               // [N]: collision candidates flagged by the brick density sweep
+    uint8_t *cflag;               // [N]: near neighbours listed by the brick density sweep
+                                  // (0..kNearCap, kNearOverflow: walk the cells)
+    uint32_t *nearq;              // [N][kNearCap]: their sorted indices
     uint32_t *key, *slot, *tmp, *pcell;
     uint32_t *idt;                // id of the particle at each scatter position (= id[tmp[.]])
     uint32_t *bframe;             // [n_bricks][128]: slot first indices, inclusive slot-count prefix
@@ -84,6 +86,9 @@ struct DevState {
 };
 
 constexpr int kMaskSlots = 16;
+// Near neighbours (within the collision distance) listed per particle for the collision step.
+constexpr int kNearCap = 6;
+constexpr int kNearOverflow = 255;
 
 // Sweep implementations: one thread per particle walking its own cell stencil, or one
 // workgroup per 2x2x2-cell brick with the brick's neighbourhood staged in LDS and the
@@ -108,7 +113,7 @@ hipError_t launch_force(const DevState &d, const Launch &L, hipStream_t st);
 // Pressure filter after launch_density, for the instances that have it on.
 hipError_t launch_filter(const DevState &d, const Launch &L, hipStream_t st);
 // Collision step on the current (drifted, cell-ordered) state, for the instances that
-// have it on; after launch_density (whose brick sweep flags the candidates); uses the
+// have it on; after launch_density (whose brick sweep lists the near neighbours); uses the
 // other velocity buffer as scratch.
 hipError_t launch_collide(const DevState &d, const Launch &L, hipStream_t st);
 hipError_t launch_load(const DevState &d, const Launch &L, hipStream_t st, const double *x,
