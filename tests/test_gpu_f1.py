@@ -203,3 +203,20 @@ def test_lone_particle(prec):
     assert abs(out["P"][0] - ref.P[0]) <= (1e-12 if prec == FP64 else 1e-6) * B
     assert np.allclose(out["x"], ref.x, rtol=0, atol=1e-14)
     assert np.array_equal(out["v"], v)
+
+
+@pytest.mark.parametrize("alpha", [1.5, 2.5])
+def test_long_collision_distance(alpha):
+    """Collision distances that defeat the density sweep's near lists: at 1.5 dx every
+    particle has more near neighbours than a list holds, at 2.5 dx (close to 2h) none is
+    listed; both take the cell walk, and match the oracle."""
+    w = _crowd(12, seed=11, f1=dict(pressure_filter=1, coll_alpha=alpha, coll_e=0.5))
+    ref = O.State.from_workload(w)
+    ref.step(1e-4, 0.0, 1)
+    s = _sim(w, MIXED, sweep=3)
+    s.step(1e-4, 0.0, 1)
+    out = s.read()
+    s.close()
+    e = field_errors(out, ref, w)
+    print(f"[f1 alpha={alpha}]", e, flush=True)
+    _assert_fields(e, 1e-5, 1)
