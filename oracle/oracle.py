@@ -180,6 +180,11 @@ class State:
         self.kind = _c(kind, np.uint8).copy()
         self.n = self.x.shape[1]
         n = self.n
+        for name, a in (("x", self.x), ("v", self.v), ("omega", self.omega)):
+            if a.shape != (3, n):
+                raise ValueError(f"{name} must be [3, {n}], got {a.shape}")
+        if self.species.shape != (n,) or self.kind.shape != (n,):
+            raise ValueError("species and kind must have n entries")
         self.rho = np.zeros(n)
         self.P = np.zeros(n)
         self.S = np.zeros(n)

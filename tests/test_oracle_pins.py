@@ -469,3 +469,149 @@ def test_generator_workloads():
     assert list(dims) == [71, 71, 35]
     w0 = I.config(0)
     assert w0.n == 4096 and abs(w0.params["c0"] - 6.656) < 0.01
+
+
+# ------------------------------------------- subset evaluation (Algorithm 1 rings) ---
+
+def _walled_cylinder(nz=12, seed=(3980, 21)):
+    """Small cylinder with jittered fluid, mixed species and spins, so every term and
+    the wall layers take part."""
+    w = I.make_cylinder(nz, seed=seed)
+    rng = np.random.default_rng(5)
+    f = w.kind == I.FLUID
+    dx = w.params["dx"]
+    w.x[:2, f] += rng.uniform(-0.2, 0.2, size=(2, int(f.sum()))) * dx
+    w.x[2, f] = np.mod(w.x[2, f] + rng.uniform(-0.2, 0.2, size=int(f.sum())) * dx, 1.0)
+    w.v[:, f] += rng.normal(0, 0.05, size=(3, int(f.sum())))
+    w.omega[:, f] = rng.normal(0, 1.0, size=(3, int(f.sum())))
+    return w
+
+
+def _jitter_periodic_box(n=11, seed=3):
+    w = I.make_box(n, kernel=I.KERNEL_WENDLAND_C2, rigid=False)
+    rng = np.random.default_rng(seed)
+    w.x = np.mod(w.x + rng.uniform(-0.3, 0.3, size=w.x.shape) / n, 1.0)
+    w.v = w.v + rng.normal(0, 0.05, size=w.v.shape)
+    w.omega = rng.normal(0, 1.0, size=w.omega.shape)
+    return w
+
+
+def _subset_ids(w, which):
+    """Particles whose neighbourhood reaches the walls (cylinder) or the periodic faces
+    (box), plus a few walls and interior particles."""
+    reach = 2 * w.params["h"]
+    if which == "cylinder":
+        r = np.hypot(w.x[0], w.x[1])
+        R_in = 1.0 - 3 * w.params["dx"]
+        near = np.flatnonzero((w.kind == I.FLUID) & (r > R_in - reach))
+        walls = np.flatnonzero(w.kind != I.FLUID)
+        inner = np.flatnonzero((w.kind == I.FLUID) & (r < 0.3))
+        pick = [near[::7], walls[::97], inner[::31]]
+    else:
+        face = np.flatnonzero(np.any((w.x < reach) | (w.x > 1.0 - reach), axis=0))
+        inner = np.flatnonzero(np.all((w.x > 0.4) & (w.x < 0.6), axis=0))
+        pick = [face[::5], inner[::3]]
+    return np.unique(np.concatenate(pick)).astype(np.int64)
+
+
+@pytest.mark.parametrize("filt", [0, 1])
+@pytest.mark.parametrize("which", ["cylinder", "box"])
+def test_eval_subset_equals_full_evaluation(which, filt):
+    """The sampled full-size checks evaluate only some particles.  They need the
+    densities of two rings of neighbours (one more with the pressure filter, whose
+    averages read the neighbours' neighbours), Algorithm 1's order density -> pressure
+    -> filter -> forces.  The subset evaluation must equal the evaluation of the whole
+    state at the same ids, bit for bit (same sums in the same order)."""
+    w = _walled_cylinder() if which == "cylinder" else _jitter_periodic_box()
+    p = dict(w.params, pressure_filter=filt, sigma_T=0.3 * w.params["rho0"] * w.params["c0"] ** 2,
+             C_l=2.0, eta=0.05)
+    ids = _subset_ids(w, which)
+    assert 40 < ids.size < w.n // 2
+    full = O.State(p, w.x, w.v, w.omega, w.species, w.kind)
+    rho, P, S, acc, alpha = O.eval_subset(p, w.x, w.v, w.omega, w.species, w.kind, ids)
+    assert np.array_equal(rho, full.rho[ids])
+    assert np.array_equal(P, full.P[ids])
+    assert np.array_equal(S, full.S[ids])
+    assert np.array_equal(acc, full.acc[:, ids])
+    assert np.array_equal(alpha, full.alpha[:, ids])
+    # the pin has teeth: the filter moves P, and the forces depend on it, by far more than
+    # any rounding
+    if filt:
+        nof = O.State(dict(p, pressure_filter=0), w.x, w.v, w.omega, w.species, w.kind)
+        fl = w.kind[ids] == I.FLUID
+        assert np.abs(nof.P[ids][fl] - P[fl]).max() > 1e-6 * np.abs(P).max()
+        assert np.abs(nof.acc[:, ids] - acc).max() > 1e-6 * np.abs(acc).max()
+
+
+# ------------------------------------------------------------ global sums -----------
+
+def _sums_state(p, w, v, omega):
+    return O.State(p, w.x, v, omega, w.species, w.kind)
+
+
+def _fluid_masses(p, w):
+    m = O.default_mass(p) if p["mass"][0] <= 0 else np.asarray(p["mass"], float)
+    return m[w.species.astype(int)], w.kind == I.FLUID
+
+
+@pytest.mark.parametrize("masses", ["equal", "unequal"])
+def test_sums_uniform_translation(masses):
+    """Every fluid particle at v0 without spin: P = M v0, J = M x_cm × v0, E = M|v0|^2/2
+    with M the fluid mass (walls, here moving, are not counted)."""
+    w = I.make_cylinder(12)
+    p = dict(w.params)
+    if masses == "unequal":
+        m0 = O.default_mass(p)[0]
+        p["mass"] = [m0, 2.5 * m0]
+    mi, f = _fluid_masses(p, w)
+    v0 = np.array([0.3, -0.7, 0.45])
+    v = np.where(f, v0[:, None], 5.0 * w.v + 1.0)
+    s = _sums_state(p, w, v, np.where(f, 0.0, 3.0) * np.ones((3, 1)))
+    P, J, E = s.diagnostics()
+    M = mi[f].sum()
+    xcm = (w.x[:, f] * mi[f]).sum(axis=1) / M
+    assert np.allclose(P, M * v0, rtol=1e-14, atol=0)
+    assert np.allclose(J, M * np.cross(xcm, v0), rtol=1e-12, atol=1e-14 * M)
+    assert abs(E - 0.5 * M * v0 @ v0) <= 1e-14 * E
+
+
+@pytest.mark.parametrize("masses", ["equal", "unequal"])
+def test_sums_uniform_spin(masses):
+    """Fluid at rest, every spin at w0: P = 0, J = (sum I) w0, E = (sum I)|w0|^2/2 with
+    I = kappa_I m dx^2 per particle."""
+    w = I.make_cylinder(12)
+    p = dict(w.params, kappa_I=0.37)
+    if masses == "unequal":
+        m0 = O.default_mass(p)[0]
+        p["mass"] = [m0, 0.4 * m0]
+    mi, f = _fluid_masses(p, w)
+    w0 = np.array([1.5, -0.5, 2.0])
+    s = _sums_state(p, w, np.where(f, 0.0, 1.0) * np.ones((3, 1)), np.where(f, w0[:, None], 7.0))
+    P, J, E = s.diagnostics()
+    Itot = (0.37 * mi[f] * p["dx"] ** 2).sum()
+    assert np.all(P == 0.0)
+    assert np.allclose(J, Itot * w0, rtol=1e-14, atol=0)
+    assert abs(E - 0.5 * Itot * w0 @ w0) <= 1e-14 * E
+
+
+def test_sums_rigid_rotation():
+    """Rigid rotation about z (v = Omega z × x, omega = Omega z): J_z is Omega times the
+    moment of inertia sum m (x^2 + y^2) plus the spin inertia, J_x = J_y = 0 on the
+    axisymmetric lattice, E = Omega^2 (sum m (x^2 + y^2) + sum I) / 2."""
+    w = I.make_cylinder(12)
+    p = dict(w.params)
+    mi, f = _fluid_masses(p, w)
+    Om = 1.7
+    v = np.stack([-Om * w.x[1], Om * w.x[0], np.zeros(w.n)])
+    omega = np.zeros((3, w.n))
+    omega[2] = Om
+    s = _sums_state(p, w, v, omega)
+    P, J, E = s.diagnostics()
+    Iorb = (mi[f] * (w.x[0, f] ** 2 + w.x[1, f] ** 2)).sum()
+    Ispin = (p["kappa_I"] * mi[f] * p["dx"] ** 2).sum()
+    M = mi[f].sum()
+    assert np.abs(P).max() < 1e-13 * M * Om
+    assert abs(J[2] - Om * (Iorb + Ispin)) <= 1e-13 * Om * Iorb
+    # J_x = -Om sum m x z and J_y = -Om sum m y z vanish by the lattice's symmetry
+    assert np.abs(J[:2]).max() < 1e-12 * Om * Iorb
+    assert abs(E - 0.5 * Om ** 2 * (Iorb + Ispin)) <= 1e-13 * E
