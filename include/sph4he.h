@@ -214,6 +214,27 @@ sph_status sph_debug_cells(sph_sim *s, uint32_t *key_by_id, uint32_t *perm,
 sph_status sph_debug_neighbors(sph_sim *s, int64_t *row_ptr, int32_t *cols, int64_t cap,
                                int64_t *nnz);
 
+/* The neighbour sets the FP32-mixed brick sweeps used at the last evaluation (Sec. 2.3
+ * neighbour particle lists), in the CSR of sph_debug_neighbors (same outputs, capacity
+ * rule and synchronisation): for the particles of bricks the density sweep staged, the hit
+ * masks it wrote and the pressure filter and the force sweep replay, decoded; for the
+ * particles it evaluated one by one, their FP64 cell walk.  The masks come from a single
+ * precision test in expanded form, |c|^2 - 2 c.t < (2h)^2 - |t|^2 on positions relative to
+ * the brick centre in units of h, so a pair may differ from the FP64 test only when
+ * |r^2 - (2h)^2| <= 1e-5 (2h)^2.  SPH_E_STATE before init, on the FP64 path, or when the
+ * last density sweep was not the brick sweep.  Meant for small n. */
+sph_status sph_debug_masks(sph_sim *s, int64_t *row_ptr, int32_t *cols, int64_t cap,
+                           int64_t *nnz);
+
+/* Near neighbours the brick density sweep listed for the collision step of Algorithm 1
+ * (pairs closer than coll_alpha dx, listed with a relative margin of 1e-4 on the squared
+ * distance; the step then tests each listed pair exactly in FP64).  Device outputs by id:
+ * count[n] (uint8: 0..6 listed, 255: not listed, the step walks the cells) and ids[n][6]
+ * (int32: the listed neighbours' ids ascending, -1 in unused places).  Synchronises.
+ * SPH_E_STATE when the collision step is off, before init, or when the last density sweep
+ * was not the brick sweep. */
+sph_status sph_debug_near(sph_sim *s, uint8_t *count, int32_t *ids);
+
 sph_status sph_set_tuning(sph_sim *s, const sph_tuning *t);
 sph_status sph_get_tuning(const sph_sim *s, sph_tuning *t);
 

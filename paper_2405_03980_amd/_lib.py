@@ -55,6 +55,8 @@ _PROTOS = {
     "sph_diagnostics": (C.c_int, [_vp, C.POINTER(C.c_double)]),
     "sph_debug_cells": (C.c_int, [_vp, _vp, _vp, _vp]),
     "sph_debug_neighbors": (C.c_int, [_vp, _vp, _vp, C.c_int64, C.POINTER(C.c_int64)]),
+    "sph_debug_masks": (C.c_int, [_vp, _vp, _vp, C.c_int64, C.POINTER(C.c_int64)]),
+    "sph_debug_near": (C.c_int, [_vp, _vp, _vp]),
     "sph_vortex_dims": (C.c_int, [C.POINTER(SphParams), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "sph_vortex_image": (C.c_int, [_vp, C.c_double, C.c_double, C.c_int32, _vp, _vp, _vp,
                                    C.POINTER(C.c_int32)]),

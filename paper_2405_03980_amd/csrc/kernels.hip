@@ -1919,13 +1919,30 @@ __global__ void k_debug_keys(DevState s, uint32_t *key_by_id, uint32_t *perm)
     if (perm) perm[p] = id;
 }
 
-// phase 0: row_ptr[id + 1] = neighbour count; phase 1: fill columns and sort each row.
-__global__ void k_debug_nbr(DevState s, int phase, int64_t *row_ptr, int32_t *cols)
+// Row of the neighbour CSR (by id): phase 0 writes the count to row_ptr[id + 1]; phase 1
+// sorts the cnt columns already written from row_ptr[id] ascending.
+__device__ __forceinline__ void nbr_row_finish(int phase, uint32_t id, int64_t cnt, int64_t *row_ptr,
+                                               int32_t *cols)
 {
-    PIdx t = map_thread(s);
-    if (!t.active) return;
-    const InstDesc *d = t.d;
-    const uint32_t p = t.p, N = s.N;
+    if (phase == 0) {
+        row_ptr[id + 1] = cnt;
+        return;
+    }
+    const int64_t base = row_ptr[id];
+    for (int64_t i = 1; i < cnt; i++) {
+        int32_t v = cols[base + i];
+        int64_t j = i - 1;
+        while (j >= 0 && cols[base + j] > v) { cols[base + j + 1] = cols[base + j]; j--; }
+        cols[base + j + 1] = v;
+    }
+}
+
+// Neighbour row of sorted particle p by its FP64 cell walk (the test of the per-particle
+// sweeps).
+__device__ __forceinline__ uint32_t nbr_walk(const DevState &s, const InstDesc *d, uint32_t p, int phase,
+                                             int64_t *row_ptr, int32_t *cols)
+{
+    const uint32_t N = s.N;
     const int cur = s.cur;
     const double *X = s.x[cur];
     const uint32_t id = s.id[cur][p];
@@ -1947,17 +1964,94 @@ __global__ void k_debug_nbr(DevState s, int phase, int64_t *row_ptr, int32_t *co
             }
         }
     });
-    if (phase == 0) {
-        row_ptr[id + 1] = cnt;
-    } else {
-        for (int64_t i = 1; i < cnt; i++) {
-            int32_t v = cols[base + i];
-            int64_t j = i - 1;
-            while (j >= 0 && cols[base + j] > v) { cols[base + j + 1] = cols[base + j]; j--; }
-            cols[base + j + 1] = v;
+    nbr_row_finish(phase, id, cnt, row_ptr, cols);
+    return err;
+}
+
+// phase 0: row_ptr[id + 1] = neighbour count; phase 1: fill columns and sort each row.
+__global__ void k_debug_nbr(DevState s, int phase, int64_t *row_ptr, int32_t *cols)
+{
+    PIdx t = map_thread(s);
+    if (!t.active) return;
+    const uint32_t err = nbr_walk(s, t.d, t.p, phase, row_ptr, cols);
+    if (err) atomicOr(s.err, err);
+}
+
+// The neighbour sets the brick density sweep used at the last evaluation (FP32-mixed
+// path), as the same CSR by id: its hit masks decoded through the stencil list of each
+// target cell (the masks the force sweep and the pressure filter replay), and the FP64
+// cell walk for the particles that sweep evaluated one by one (bricks too large to stage,
+// stencils longer than its windows).  One workgroup per brick, laid out as in the sweep.
+__global__ void __launch_bounds__(kBrickThreads) k_debug_masks(DevState s, int phase, int64_t *row_ptr,
+                                                               int32_t *cols)
+{
+    __shared__ BrickFrame F;
+    __shared__ int16_t tbl[kBrickThreads / 64][kCandWin][64];
+    const uint32_t brick = blockIdx.x;
+    const uint32_t bxyz = s.brick_xyz[brick];
+    const InstDesc *d = s.desc + s.brick_inst[brick];
+    brick_frame(s, d, brick, bxyz, F, kStageDensity);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int ts[3];
+    if (!brick_target(d, bxyz, w, ts)) return;
+    const int tslot = slot_index(ts[0], ts[1], ts[2]);
+    const uint32_t pbase = F.begin[tslot], nt = F.off[tslot + 1] - F.off[tslot];
+    uint32_t err = 0;
+    bool walk = !F.ok;
+    StencilList S{0, 0, 0};
+    if (!walk && nt) {
+        S = stencil_list(F, ts, lane, &tbl[w][0][0]);
+        walk = S.NW > (uint32_t)kCandWin;
+    }
+    for (uint32_t i = lane; i < nt; i += 64) {
+        const uint32_t p = pbase + i;
+        if (walk) {
+            err |= nbr_walk(s, d, p, phase, row_ptr, cols);
+            continue;
         }
+        const uint32_t id = s.id[s.cur][p];
+        const int64_t base = phase ? row_ptr[id] : 0;
+        int64_t cnt = 0;
+        for (uint32_t c = 0; c < S.NW; c++) {
+            uint64_t m = s.masks[(size_t)p * kMaskSlots + c];
+            while (m) {
+                const int j = __builtin_ctzll(m);
+                m &= m - 1;
+                if (phase) {
+                    const uint32_t k = (uint32_t)tbl[w][c][j];
+                    const int sl = slot_of(F, k);
+                    cols[base + cnt] = (int32_t)s.id[s.cur][F.begin[sl] + (k - F.off[sl])];
+                }
+                cnt++;
+            }
+        }
+        nbr_row_finish(phase, id, cnt, row_ptr, cols);
     }
     if (err) atomicOr(s.err, err);
+}
+
+// Near neighbours listed by the brick density sweep for the collision step, by id:
+// count[id] = the number listed (kNearOverflow: not listed, the step walks the cells) and
+// ids[id][0 .. count) their ids, ascending (-1 in the unused places).
+__global__ void k_debug_near(DevState s, uint8_t *count, int32_t *ids)
+{
+    PIdx t = map_thread(s);
+    if (!t.active) return;
+    const uint32_t p = t.p;
+    const uint32_t id = s.id[s.cur][p];
+    const uint32_t n = s.cflag[p];
+    count[id] = (uint8_t)n;
+    int32_t v[kNearCap];
+    for (int a = 0; a < kNearCap; a++) v[a] = -1;
+    if (n <= (uint32_t)kNearCap) {
+        for (uint32_t a = 0; a < n; a++) {
+            int32_t x = (int32_t)s.id[s.cur][s.nearq[(size_t)p * kNearCap + a]];
+            uint32_t b = a;
+            for (; b > 0 && v[b - 1] > x; b--) v[b] = v[b - 1];
+            v[b] = x;
+        }
+    }
+    for (int a = 0; a < kNearCap; a++) ids[(size_t)id * kNearCap + a] = v[a];
 }
 
 // ------------------------------------------------------------ diagnostics -----------
@@ -2471,6 +2565,21 @@ hipError_t launch_debug_nbr(const DevState &d, const Launch &L, hipStream_t st, 
                             int64_t *row_ptr, int32_t *cols)
 {
     k_debug_nbr<<<grid_for(d.n_waves, L.bs_stream), L.bs_stream, 0, st>>>(d, phase, row_ptr, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_masks(const DevState &d, hipStream_t st, int phase, int64_t *row_ptr,
+                              int32_t *cols)
+{
+    if (!d.n_bricks) return hipErrorInvalidValue;
+    k_debug_masks<<<d.n_bricks, kBrickThreads, 0, st>>>(d, phase, row_ptr, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_near(const DevState &d, const Launch &L, hipStream_t st, uint8_t *count,
+                             int32_t *ids)
+{
+    k_debug_near<<<grid_for(d.n_waves, L.bs_stream), L.bs_stream, 0, st>>>(d, count, ids);
     return hipGetLastError();
 }
 

@@ -857,16 +857,20 @@ sph_status sph_debug_cells(sph_sim *s, uint32_t *key_by_id, uint32_t *perm, uint
     return SPH_OK;
 }
 
-sph_status sph_debug_neighbors(sph_sim *s, int64_t *row_ptr, int32_t *cols, int64_t cap, int64_t *nnz)
+}  // extern "C"
+
+namespace {
+
+// Neighbour CSR by id in two launches (counts, then columns), with the host prefix sum in
+// between; `launch(phase, row_ptr, cols)` enqueues one phase.
+template <class Launcher>
+sph_status neighbour_csr(sph_batch *b, int64_t *row_ptr, int32_t *cols, int64_t cap, int64_t *nnz,
+                         Launcher &&launch)
 {
-    if (!s) return SPH_E_INVALID;
-    sph_batch *b = s->b;
-    if (!row_ptr || !nnz || cap < 0 || (cap > 0 && !cols)) { b->err = "bad neighbour output"; return SPH_E_INVALID; }
-    if (!b->loaded) { b->err = "debug before init"; return SPH_E_STATE; }
     const size_t n = b->ds.N;
     hipError_t e = hipMemsetAsync(row_ptr, 0, sizeof(int64_t), b->stream);
     if (e != hipSuccess) return hip_fail(e, b->err, "clear row_ptr");
-    sph_status st = check_launch(b, launch_debug_nbr(b->ds, b->L, b->stream, 0, row_ptr, cols), "neighbour count");
+    sph_status st = check_launch(b, launch(0, row_ptr, cols), "neighbour count");
     if (st != SPH_OK) return st;
     std::vector<int64_t> h(n + 1);
     e = hipMemcpyAsync(h.data(), row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, b->stream);
@@ -879,7 +883,60 @@ sph_status sph_debug_neighbors(sph_sim *s, int64_t *row_ptr, int32_t *cols, int6
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return hip_fail(e, b->err, "row_ptr upload");
     if (h[n] > cap) { b->err = "neighbour capacity too small"; return SPH_E_CAPACITY; }
-    st = check_launch(b, launch_debug_nbr(b->ds, b->L, b->stream, 1, row_ptr, cols), "neighbour fill");
+    st = check_launch(b, launch(1, row_ptr, cols), "neighbour fill");
+    if (st != SPH_OK) return st;
+    return batch_sync(b);
+}
+
+sph_status neighbour_args(sph_batch *b, int64_t *row_ptr, int32_t *cols, int64_t cap, int64_t *nnz)
+{
+    if (!row_ptr || !nnz || cap < 0 || (cap > 0 && !cols)) { b->err = "bad neighbour output"; return SPH_E_INVALID; }
+    if (!b->loaded) { b->err = "debug before init"; return SPH_E_STATE; }
+    return SPH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sph_status sph_debug_neighbors(sph_sim *s, int64_t *row_ptr, int32_t *cols, int64_t cap, int64_t *nnz)
+{
+    if (!s) return SPH_E_INVALID;
+    sph_batch *b = s->b;
+    sph_status st = neighbour_args(b, row_ptr, cols, cap, nnz);
+    if (st != SPH_OK) return st;
+    return neighbour_csr(b, row_ptr, cols, cap, nnz, [&](int phase, int64_t *r, int32_t *c) {
+        return launch_debug_nbr(b->ds, b->L, b->stream, phase, r, c);
+    });
+}
+
+sph_status sph_debug_masks(sph_sim *s, int64_t *row_ptr, int32_t *cols, int64_t cap, int64_t *nnz)
+{
+    if (!s) return SPH_E_INVALID;
+    sph_batch *b = s->b;
+    sph_status st = neighbour_args(b, row_ptr, cols, cap, nnz);
+    if (st != SPH_OK) return st;
+    if (!b->masks_current) {
+        b->err = "the last density sweep was not the brick sweep: no hit masks";
+        return SPH_E_STATE;
+    }
+    return neighbour_csr(b, row_ptr, cols, cap, nnz, [&](int phase, int64_t *r, int32_t *c) {
+        return launch_debug_masks(b->ds, b->stream, phase, r, c);
+    });
+}
+
+sph_status sph_debug_near(sph_sim *s, uint8_t *count, int32_t *ids)
+{
+    if (!s) return SPH_E_INVALID;
+    sph_batch *b = s->b;
+    if (!count || !ids) { b->err = "bad near-list output"; return SPH_E_INVALID; }
+    if (!b->loaded) { b->err = "debug before init"; return SPH_E_STATE; }
+    if (!b->masks_current || !b->ds.any_coll) {
+        b->err = "no near lists: the collision step is off or the last density sweep was not "
+                 "the brick sweep";
+        return SPH_E_STATE;
+    }
+    sph_status st = check_launch(b, launch_debug_near(b->ds, b->L, b->stream, count, ids), "near lists");
     if (st != SPH_OK) return st;
     return batch_sync(b);
 }

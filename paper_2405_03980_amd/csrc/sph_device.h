@@ -127,6 +127,13 @@ hipError_t launch_debug_keys(const DevState &d, const Launch &L, hipStream_t st,
                              uint32_t *key_by_id, uint32_t *perm);
 hipError_t launch_debug_nbr(const DevState &d, const Launch &L, hipStream_t st, int phase,
                             int64_t *row_ptr, int32_t *cols);
+// The neighbour sets of the last brick density sweep (its decoded hit masks; the FP64 walk
+// where it evaluated per particle), same two phases and CSR as launch_debug_nbr.
+hipError_t launch_debug_masks(const DevState &d, hipStream_t st, int phase, int64_t *row_ptr,
+                              int32_t *cols);
+// The near-neighbour lists of the last brick density sweep (collision step), by id.
+hipError_t launch_debug_near(const DevState &d, const Launch &L, hipStream_t st, uint8_t *count,
+                             int32_t *ids);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st);
 
 // Vortex diagnostic of one instance (the first): section z0, pixel grid nx x ny of side

@@ -151,6 +151,29 @@ class Simulation:
         _check(st, "sph_debug_neighbors", self._err)
         return row.cpu().numpy(), cols[: nnz.value].cpu().numpy()
 
+    def debug_masks(self, cap: int | None = None):
+        """Neighbour CSR by id of the hit masks the FP32-mixed brick sweeps used."""
+        cap = cap if cap is not None else 200 * self.n
+        with torch.cuda.stream(self.stream):
+            row = torch.empty(self.n + 1, dtype=torch.int64, device=self.device)
+            cols = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+        nnz = C.c_int64(0)
+        st = self.lib.sph_debug_masks(self._h, row.data_ptr(), cols.data_ptr(), C.c_int64(cap),
+                                      C.byref(nnz))
+        if st == L.E_CAPACITY and cap < nnz.value:
+            return self.debug_masks(int(nnz.value))
+        _check(st, "sph_debug_masks", self._err)
+        return row.cpu().numpy(), cols[: nnz.value].cpu().numpy()
+
+    def debug_near(self):
+        """(count uint8 [n], ids int32 [n, 6]) of the near lists of the collision step."""
+        with torch.cuda.stream(self.stream):
+            cnt = torch.empty(self.n, dtype=torch.uint8, device=self.device)
+            ids = torch.empty((self.n, 6), dtype=torch.int32, device=self.device)
+        _check(self.lib.sph_debug_near(self._h, cnt.data_ptr(), ids.data_ptr()), "sph_debug_near",
+               self._err)
+        return cnt.cpu().numpy(), ids.cpu().numpy()
+
     def vortex_image(self, z0: float = 0.0, theta: float = 0.5, min_pixels: int = 4,
                      to_numpy: bool = True):
         """(count, image [ny, nx], labels [ny, nx]) of the rotational-force intensity on the
