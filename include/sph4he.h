@@ -201,6 +201,19 @@ sph_status sph_vortex_dims(const sph_params *p, int32_t *nx, int32_t *ny);
 sph_status sph_vortex_image(sph_sim *s, double z0, double theta, int32_t min_pixels,
                             double *image, int32_t *labels, int32_t *scratch, int32_t *count);
 
+/* sph_vortex_image without the scratch argument, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid allocation).
+ * It calls no hipMalloc, hipFree or other allocating routine: its scratch is a static
+ * device array of the library, 2^20 + 8 int32 (4 MiB) per device, held by each device the
+ * library runs on until the process ends.  image and labels stay caller-owned as in
+ * sph_vortex_image; images of more than 2^20 pixels (nx ny from sph_vortex_dims) return
+ * SPH_E_CAPACITY before anything is enqueued.  Results equal sph_vortex_image's.  Calls
+ * on one device share that array, so two calls that overlap on one device (two host
+ * threads, or two streams without ordering) race; calls one after the other are safe, the
+ * array is cleared at the start of each call. */
+sph_status sph_vortex_image_noalloc(sph_sim *s, double z0, double theta, int32_t min_pixels,
+                                    double *image, int32_t *labels, int32_t *count);
+
 /* Cell list of the last neighbour search (device outputs).  key_by_id[n]: Morton code of
  * the particle's cell (bit 0 = x); perm[n]: particle ids sorted by (key, id);
  * cell_start[ncell + 1]: CSR offsets of the cells taken in Morton order, ncell being the

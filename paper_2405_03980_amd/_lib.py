@@ -60,6 +60,8 @@ _PROTOS = {
     "sph_vortex_dims": (C.c_int, [C.POINTER(SphParams), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "sph_vortex_image": (C.c_int, [_vp, C.c_double, C.c_double, C.c_int32, _vp, _vp, _vp,
                                    C.POINTER(C.c_int32)]),
+    "sph_vortex_image_noalloc": (C.c_int, [_vp, C.c_double, C.c_double, C.c_int32, _vp, _vp,
+                                           C.POINTER(C.c_int32)]),
     "sph_set_tuning": (C.c_int, [_vp, C.POINTER(SphTuning)]),
     "sph_get_tuning": (C.c_int, [_vp, C.POINTER(SphTuning)]),
     "sph_sync": (C.c_int, [_vp]),

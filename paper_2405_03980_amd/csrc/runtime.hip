@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -365,6 +366,7 @@ struct sph_batch {
                                  // hold the neighbours of the current positions)
     double pending_dt = 0.0;  // closing half kick of this dt still to apply
     bool use_graph = true;
+    int device = 0;           // device current at creation (the workspace's)
     GraphCache graphs[2];
     std::string err;
     uint32_t host_err = 0;
@@ -646,8 +648,11 @@ sph_status sph_batch_create(int32_t n_inst, const sph_params *params, const int6
     DevState d{};
     carve(c, d, n_inst, pl.N, pl.C, pl.n_bricks, params[0].precision, pl.any_filter, pl.any_coll);
     if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || ws_bytes < c.off) return SPH_E_WORKSPACE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SPH_E_HIP;
     sph_batch *b = new (std::nothrow) sph_batch();
     if (!b) return SPH_E_INVALID;
+    b->device = dev;
     b->stream = (hipStream_t)hip_stream;
     b->n_inst = n_inst;
     b->desc = pl.desc;
@@ -974,18 +979,28 @@ sph_status sph_vortex_dims(const sph_params *p, int32_t *nx, int32_t *ny)
     return SPH_OK;
 }
 
-sph_status sph_vortex_image(sph_sim *s, double z0, double theta, int32_t min_pixels,
-                            double *image, int32_t *labels, int32_t *scratch, int32_t *count)
+}  // extern "C"
+
+namespace {
+
+sph_status vortex_args(sph_batch *b, double z0, double theta, int32_t min_pixels, double *image,
+                       int32_t *labels, int32_t *count)
 {
-    if (!s) return SPH_E_INVALID;
-    sph_batch *b = s->b;
-    if (!image || !labels || !scratch || !count || !std::isfinite(z0) || !std::isfinite(theta) ||
-        theta < 0.0 || min_pixels < 1 || ((uintptr_t)scratch & 7u)) {
-        b->err = "vortex image: needs image, labels, 8-byte aligned scratch and count, finite z0, "
-                 "theta >= 0 and min_pixels >= 1";
+    if (!image || !labels || !count || !std::isfinite(z0) || !std::isfinite(theta) ||
+        theta < 0.0 || min_pixels < 1) {
+        b->err = "vortex image: needs image, labels and count, finite z0, theta >= 0 and "
+                 "min_pixels >= 1";
         return SPH_E_INVALID;
     }
     if (!b->loaded) { b->err = "vortex image before init"; return SPH_E_STATE; }
+    return SPH_OK;
+}
+
+// The vortex image, labels and count with the given scratch (int32, nx ny + 8, 8-byte
+// aligned, device memory; cleared here before use).
+sph_status vortex_image(sph_batch *b, double z0, double theta, int32_t min_pixels, double *image,
+                        int32_t *labels, int32_t *scr, int32_t *count)
+{
     const sph_params &p = b->params[0];
     int32_t nx, ny;
     vortex_grid(p, nx, ny);
@@ -1000,13 +1015,13 @@ sph_status sph_vortex_image(sph_sim *s, double z0, double theta, int32_t min_pix
     a.nx = nx;
     a.ny = ny;
     // scratch: size[n] | changed | count | (8-byte aligned) image maximum
-    int32_t *size = scratch;
-    uint32_t *changed = (uint32_t *)(scratch + n);
-    int32_t *cnt = scratch + n + 1;
-    unsigned long long *vmax = (unsigned long long *)(scratch + ((n + 3) & ~1u));
+    int32_t *size = scr;
+    uint32_t *changed = (uint32_t *)(scr + n);
+    int32_t *cnt = scr + n + 1;
+    unsigned long long *vmax = (unsigned long long *)(scr + ((n + 3) & ~1u));
     unsigned long long *img = (unsigned long long *)image;
     hipError_t e = launch_fill_u32((uint32_t *)image, 0u, 2 * (size_t)n, b->stream);
-    if (e == hipSuccess) e = launch_fill_u32((uint32_t *)scratch, 0u, ((n + 3) & ~1u) + 2, b->stream);
+    if (e == hipSuccess) e = launch_fill_u32((uint32_t *)scr, 0u, ((n + 3) & ~1u) + 2, b->stream);
     if (e == hipSuccess) e = launch_vortex_intensity(b->ds, b->L, b->stream, a, b->masks_current, img, vmax);
     if (e == hipSuccess) e = launch_vortex_label_init(b->stream, img, vmax, theta, n, labels);
     if (e != hipSuccess) return hip_fail(e, b->err, "vortex image");
@@ -1030,6 +1045,75 @@ sph_status sph_vortex_image(sph_sim *s, double z0, double theta, int32_t min_pix
     if (e == hipSuccess) e = hipMemcpyAsync(count, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, b->stream);
     if (e != hipSuccess) return hip_fail(e, b->err, "vortex count");
     return batch_sync(b);
+}
+
+// Scratch of sph_vortex_image_noalloc: one array per device, held until the process ends.
+constexpr uint32_t kVortexPixelsMax = 1u << 20;
+constexpr size_t kVortexScratchInts = (size_t)kVortexPixelsMax + 8;
+__device__ __align__(256) int32_t scratch[kVortexScratchInts];
+
+// Device address of `scratch` on each device, looked up once per device with that device
+// current (in host code the array's name is not a device address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int32_t *g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_on(int dev, int32_t **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = (int32_t *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+sph_status sph_vortex_image(sph_sim *s, double z0, double theta, int32_t min_pixels,
+                            double *image, int32_t *labels, int32_t *scratch_buf, int32_t *count)
+{
+    if (!s) return SPH_E_INVALID;
+    sph_batch *b = s->b;
+    sph_status st = vortex_args(b, z0, theta, min_pixels, image, labels, count);
+    if (st != SPH_OK) return st;
+    if (!scratch_buf || ((uintptr_t)scratch_buf & 7u)) {
+        b->err = "vortex image: needs an 8-byte aligned scratch buffer";
+        return SPH_E_INVALID;
+    }
+    return vortex_image(b, z0, theta, min_pixels, image, labels, scratch_buf, count);
+}
+
+sph_status sph_vortex_image_noalloc(sph_sim *s, double z0, double theta, int32_t min_pixels,
+                                    double *image, int32_t *labels, int32_t *count)
+{
+    if (!s) return SPH_E_INVALID;
+    sph_batch *b = s->b;
+    sph_status st = vortex_args(b, z0, theta, min_pixels, image, labels, count);
+    if (st != SPH_OK) return st;
+    int32_t nx, ny;
+    vortex_grid(b->params[0], nx, ny);
+    if ((uint64_t)nx * (uint64_t)ny > (uint64_t)kVortexPixelsMax) {
+        b->err = "vortex image (no-alloc): more than 2^20 pixels";
+        return SPH_E_CAPACITY;
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, b->err, "current device");
+    const bool other = dev != b->device;
+    if (other && (e = hipSetDevice(b->device)) != hipSuccess) return hip_fail(e, b->err, "set device");
+    int32_t *scr = nullptr;
+    e = scratch_on(b->device, &scr);
+    if (e == hipSuccess) st = vortex_image(b, z0, theta, min_pixels, image, labels, scr, count);
+    else st = hip_fail(e, b->err, "scratch address");
+    if (other) (void)hipSetDevice(dev);
+    return st;
 }
 
 const char *sph_last_error(const sph_sim *s)
