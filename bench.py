@@ -1,21 +1,24 @@
 #!/usr/bin/env python
 """Throughput of the two-fluid SPH step on one MI355X.
 
-Workload: the 19.57M-particle rotating cylinder (R = H = 1, dx = 1/184, Wendland C2,
-h = 1.3 dx, 70/30 inviscid/viscous fluid, three wall layers turning at Omega = 1, fluid at
-rest plus N(0, 1e-3) noise), FP32-mixed path, dt = 1e-4.  A step is one velocity-Verlet
+Headline workload: the 19.57M-particle rotating cylinder (R = H = 1, dx = 1/184, Wendland
+C2, h = 1.3 dx, 70/30 inviscid/viscous fluid, three wall layers turning at Omega = 1, fluid
+at rest plus N(0, 1e-3) noise), FP32-mixed path, dt = 1e-4.  A step is one velocity-Verlet
 step of every particle: kick/drift, cell list, density/EOS, forces/torques.
 
-Prints ONE JSON line: particle-updates/s (walls included, as the paper counts particles),
-the per-kernel roofline of the dominant kernel from HIP events recorded on the library's
-stream during the timed steps, the FP64 GPU path's step time, and the FP64 CPU oracle
-timed on a bounded sample of the same workload.
+Prints ONE JSON line: particle-updates/s (walls included, as the paper counts particles;
+median of three timed runs of --steps steps), the roofline of the dominant kernel (the
+force sweep) from HIP events recorded on the library's stream during a further profiled
+run, the whole step's HBM fraction, every configuration of the measurement plan timed on
+the GPU (FP64 and FP32-mixed, median of three runs), and the FP64 CPU oracle timed on the
+host (one step of the headline workload; configurations 0 and 1 beside it).
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -25,24 +28,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Vector peak without packed FP32: 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz.
-VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# MI355X published FP32 vector peak (packed FP32) and the rate without packed FP32
+# instructions, which this build does not emit: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz.
+FP32_PEAK_TFLOPS = 157.3
+FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
-# Algorithmic work per fluid particle and step, FP32-mixed path:
-# 80 neighbours on the lattice (r < 2h = 2.6 dx); flops of one evaluation of the pair
-# formula averaged over the species mix (unlike pairs 42 %, viscous-viscous 9 %).
-NEIGHBOURS = 80
-FORCE_FLOPS_PER_PAIR = 52
-DENSITY_FLOPS_PER_PAIR = 19
-# Compulsory HBM bytes per particle of each kernel group (mixed precision).
-BYTES_PER_PARTICLE = {
+# Compulsory HBM bytes per particle-update of the FP32-mixed step (the algorithmic count of
+# the measurement plan): the force sweep reads x, v, w (72), rho, P, S (12), species (1),
+# its cell index (4) and writes a, alpha (24); the whole step moves about 350 B.
+FORCE_BYTES_PER_PU = 113
+STEP_BYTES_PER_PU = 350
+# Algorithmic flops of the force sweep per particle-update: about 84 per unique pair
+# (distance 9, pair terms 75 averaged over the species mix) over 40 unique pairs.
+FORCE_FLOPS_PER_PU = 84 * 40
+# Our own per-kernel counts of compulsory bytes per particle (mixed precision), for the
+# per-kernel table.
+KERNEL_BYTES_PER_PARTICLE = {
     "keys": 24 + 24 + 12 + 1 + 4 + 4,          # x, v, acc, sk -> key, slot
-    "scan": 0.0,                                # per cell, counted below
     "scatter": 4 + 4 + 4 + 4 + 4 + 4,           # key, slot, start, id -> tmp, idt
     "reorder": 4 + 4 + 4 + 72 + 24 + 1 + 72 + 4 + 1 + 4,  # tmp, key, id, state -> state, pcell
     "density": 24 + 1 + 4 + 4 + 16 + 8,         # x, sk, pcell, cell_xyz -> aux, rho/P
-    "force": 72 + 16 + 1 + 4 + 4 + 24,          # x, v, w, aux, sk, pcell, cell -> acc, alpha
+    "force": FORCE_BYTES_PER_PU,
 }
+GOLD100 = os.path.join(ROOT, "tests", "golden", "cylinder_2p45M_100steps.npz")
+TUNING_KEYS = ("block_density", "block_force", "block_stream", "use_graph", "sweep")
 
 
 def parse():
@@ -50,19 +59,25 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--runs", type=int, default=3, help="timed runs per figure (median)")
     ap.add_argument("--nz", type=int, default=184, help="cylinder resolution (184: 19.57M)")
-    ap.add_argument("--fp64-steps", type=int, default=5)
-    ap.add_argument("--cpu-steps", type=int, default=32)
+    ap.add_argument("--fp64-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the smaller configurations (0-2) of the measurement plan")
     ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2405_03980_amd", "tuned.json"))
     ap.add_argument("--f1-steps", type=int, default=20,
                     help="timed steps with the pressure filter and the collision step on (0: skip)")
-    ap.add_argument("--batch-steps", type=int, default=20,
+    ap.add_argument("--batch-steps", type=int, default=100,
                     help="steps of the batched 64-instance ensemble (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="only run a plain device-to-device copy of this size (5 times), to "
                          "calibrate the HBM traffic counters, and exit")
     return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def copy_calibration(mib: int) -> None:
@@ -78,9 +93,6 @@ def copy_calibration(mib: int) -> None:
     print(json.dumps({"copy_calibration_MiB": mib, "bytes_per_copy": 4 * n}), flush=True)
 
 
-TUNING_KEYS = ("block_density", "block_force", "block_stream", "use_graph", "sweep")
-
-
 def load_tuning(path, name):
     """Tuned settings of a workload: (launch tuning for sph_tuning, cell factor)."""
     try:
@@ -89,24 +101,6 @@ def load_tuning(path, name):
     except (OSError, ValueError):
         t = {}
     return {k: v for k, v in t.items() if k in TUNING_KEYS}, int(t.get("cell_factor", 1))
-
-
-def cpu_baseline(nz: int, steps: int) -> dict:
-    """The FP64 oracle on an 8-layer z-slab of the same cylinder (same dx, kernel, species
-    mix and wall layers, z periodic over the slab): its per-particle cost is the full
-    workload's; the rate is particle-updates per second of wall time on the host."""
-    from oracle import oracle as O
-    from paper_2405_03980_amd import inputs as I
-    layers = 8
-    w = I.make_cylinder(layers, H=layers / nz, seed=(3980, 3))
-    s = O.State.from_workload(w)
-    t0 = time.perf_counter()
-    s.step(1e-4, 1.0, steps)
-    dt = time.perf_counter() - t0
-    return {"value": w.n * steps / dt, "unit": "particle-updates/s", "cores": O.num_threads(),
-            "kind": "oracle",
-            "sample": f"{steps} steps of an {layers}-layer z-slab ({w.n} particles) of the "
-                      f"nz={nz} cylinder, FP64, {dt:.1f} s"}
 
 
 def kernel_source_sha() -> str:
@@ -133,7 +127,98 @@ def measured_traffic(kernel: str):
     return 1024.0 * (k["FETCH_SIZE_KiB"] * c["fetch_scale"] + k["WRITE_SIZE_KiB"] * c["write_scale"])
 
 
-def batch_bench(steps: int, tuning_path: str) -> dict:
+def _sync_all(obj):
+    import torch
+    obj.sync()
+    torch.cuda.synchronize()
+
+
+def time_runs(obj, Om, steps: int, runs: int) -> list[float]:
+    """Seconds of `runs` timed runs of `steps` steps each, every run bracketed by a stream
+    and device synchronisation."""
+    out = []
+    for _ in range(runs):
+        _sync_all(obj)
+        t0 = time.perf_counter()
+        obj.step(1e-4, Om, steps)
+        _sync_all(obj)
+        out.append(time.perf_counter() - t0)
+    return out
+
+
+def profile_run(obj, Om, steps: int) -> dict:
+    """Per-kernel milliseconds per step from HIP events on the library's stream."""
+    _sync_all(obj)
+    obj.profile_begin()
+    obj.step(1e-4, Om, steps)
+    ms, n = obj.profile_end()
+    _sync_all(obj)
+    return {k: v / n for k, v in ms.items() if v}
+
+
+def simulation(w, precision, tuning, extra=None):
+    from paper_2405_03980_amd import sim as S
+    tun, cf = tuning
+    s = S.Simulation(dict(w.params, cell_factor=cf, **(extra or {})), w.n, precision=precision)
+    if tun:
+        s.set_tuning(**tun)
+    s.init(w.x, w.v, w.omega, w.species, w.kind)
+    return s
+
+
+def timed_config(w, precision, steps, warmup, runs, tuning, profile=False, fields=None):
+    """ms/step (median of `runs`), PU/s, optional per-kernel ms and fields read after the
+    first run (warmup + steps steps from the initial state)."""
+    import torch
+    s = simulation(w, precision, tuning)
+    s.step(1e-4, w.Omega, warmup)
+    t = time_runs(s, w.Omega, steps, 1)
+    got = s.read(fields) if fields else None
+    t += time_runs(s, w.Omega, steps, runs - 1)
+    med = statistics.median(t)
+    out = {"ms_per_step": round(1e3 * med / steps, 4), "value": w.n * steps / med,
+           "runs_ms_per_step": [round(1e3 * x / steps, 4) for x in t], "steps": steps,
+           "warmup": warmup}
+    if profile:
+        out["kernel_ms"] = {k: round(v, 4) for k, v in profile_run(s, w.Omega, steps).items()}
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return out, got
+
+
+def field_errors(a: dict, b: dict, fluid, B) -> dict:
+    """Normwise relative difference of a against b over fluid particles (P over B)."""
+    out = {}
+    for k in ("rho", "P", "v", "omega", "acc"):
+        x, y = a[k][..., fluid], b[k][..., fluid]
+        if k == "P":
+            out[k] = float(np.abs(x - y).max() / B)
+            continue
+        if x.ndim == 2:
+            d, r = np.sqrt(((x - y) ** 2).sum(0)), np.sqrt((y * y).sum(0))
+        else:
+            d, r = np.abs(x - y), np.abs(y)
+        out[k] = float(d.max() / max(r.max(), 1e-300))
+    return out
+
+
+def golden_errors(out: dict, w) -> dict:
+    """Errors against the stored FP64 oracle sample of the 2.45M cylinder after 100 steps
+    (5,000 fluid particles, normwise over the oracle's whole-field maxima)."""
+    g = np.load(GOLD100, allow_pickle=False)
+    ids = g["ids"]
+    p = w.params
+    B = p["rho0"] * p["c0"] ** 2 / 7.0
+    nrm = lambda a: np.sqrt((a * a).sum(axis=0))
+    e = {"rho": float(np.abs(out["rho"][ids] - g["rho"]).max() / g["rho_max"]),
+         "P": float(np.abs(out["P"][ids] - g["P"]).max() / B)}
+    for k in ("v", "omega", "acc"):
+        e[k] = float(nrm(out[k][:, ids] - g[k]).max() / g[k + "_max"])
+    return e
+
+
+def batch_bench(steps: int, runs: int, tuning_path: str) -> dict:
     """The 64-instance ensemble (20k-300k particles each, viscous fraction 0.05-0.5,
     Omega 0.5-2), FP32-mixed: all instances in shared launches replayed from a hipGraph,
     against the same instances stepped one after another."""
@@ -150,15 +235,11 @@ def batch_bench(steps: int, tuning_path: str) -> dict:
     if tun:
         b.set_tuning(**tun)
     b.step(1e-4, Om, 4)
-    b.sync()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.step(1e-4, Om, steps)
-    b.sync()
-    el = time.perf_counter() - t0
+    t = time_runs(b, Om, steps, runs)
+    kms = profile_run(b, Om, max(10, steps // 5))
     b.close()
     del b
-    seq_steps = max(2, steps // 4)
+    seq_steps = max(2, steps // 10)
     sims = [S.simulation_from(w) for w in ws]
     for s_, w in zip(sims, ws):
         s_.step(1e-4, w.Omega, 2)
@@ -176,25 +257,27 @@ def batch_bench(steps: int, tuning_path: str) -> dict:
         s_.close()
     del sims
     torch.cuda.empty_cache()
-    ms = 1e3 * el / steps
+    med = statistics.median(t)
+    ms = 1e3 * med / steps
     ms_seq = 1e3 * el_seq / seq_steps
-    return {"value": N * steps / el, "unit": "particle-updates/s", "n_inst": len(ws),
-            "tuning": tun or "default", "cell_factor": cf,
-            "particles": N, "ms_per_step": round(ms, 3), "sequential_ms_per_step": round(ms_seq, 3),
+    return {"value": N * steps / med, "unit": "particle-updates/s", "n_inst": len(ws),
+            "tuning": tun or "default", "cell_factor": cf, "particles": N, "steps": steps,
+            "ms_per_step": round(ms, 4), "runs_ms_per_step": [round(1e3 * x / steps, 4) for x in t],
+            "kernel_ms": {k: round(v, 4) for k, v in kms.items()},
+            "sequential_ms_per_step": round(ms_seq, 3),
             "speedup_vs_sequential": round(ms_seq / ms, 2)}
 
 
-def field_errors(a: dict, b: dict, fluid) -> dict:
-    """Normwise relative difference of a against b over fluid particles."""
-    out = {}
-    for k in ("rho", "P", "v", "omega", "acc"):
-        x, y = a[k][..., fluid], b[k][..., fluid]
-        if x.ndim == 2:
-            d, r = np.sqrt(((x - y) ** 2).sum(0)), np.sqrt((y * y).sum(0))
-        else:
-            d, r = np.abs(x - y), np.abs(y)
-        out[k] = float(d.max() / max(r.max(), 1e-300))
-    return out
+def oracle_rate(w, steps: int) -> dict:
+    """The FP64 oracle as it stands on the host's threads: particle-updates per second of
+    `steps` steps (its evaluation at load excluded)."""
+    from oracle import oracle as O
+    s = O.State.from_workload(w)
+    t0 = time.perf_counter()
+    s.step(1e-4, w.Omega, steps)
+    dt = time.perf_counter() - t0
+    return {"value": w.n * steps / dt, "unit": "particle-updates/s", "cores": O.num_threads(),
+            "kind": "oracle", "steps": steps, "seconds": round(dt, 2), "particles": w.n}
 
 
 def main():
@@ -209,108 +292,130 @@ def main():
     import torch
     from paper_2405_03980_amd import _lib as L
     from paper_2405_03980_amd import inputs as I
-    from paper_2405_03980_amd import sim as S
 
     w = I.make_cylinder(args.nz, seed=(3980, 3))
     name = f"cylinder_nz{args.nz}"
     n, nf = w.n, w.n_fluid
-    print(f"[bench] {name}: {n} particles ({nf} fluid)", file=sys.stderr, flush=True)
-
-    def run(precision, steps, warmup, tuning, vortex=False, extra=None):
-        tun, cf = tuning
-        s = S.Simulation(dict(w.params, cell_factor=cf, **(extra or {})), w.n, precision=precision)
-        if tun:
-            s.set_tuning(**tun)
-        s.init(w.x, w.v, w.omega, w.species, w.kind)
-        s.step(1e-4, w.Omega, warmup)
-        s.sync()
-        torch.cuda.synchronize()
-        s.profile_begin()
-        t0 = time.perf_counter()
-        s.step(1e-4, w.Omega, steps)
-        ms, nsteps = s.profile_end()
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t0
-        s.sync()
-        fields = s.read(("rho", "P", "v", "omega", "acc"))
-        if vortex:
-            # the vortex diagnostic of the z = 0 section on the state just stepped
-            s.vortex_image(0.0, 0.5, 3, to_numpy=False)  # warm-up
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            cnt, img, _ = s.vortex_image(0.0, 0.5, 3, to_numpy=False)
-            torch.cuda.synchronize()
-            fields["vortex"] = {"ms": round(1e3 * (time.perf_counter() - t1), 3), "z0": 0.0,
-                                "theta": 0.5, "min_pixels": 3, "count": cnt,
-                                "image": [int(img.shape[0]), int(img.shape[1])]}
-        s.close()
-        del s
-        torch.cuda.empty_cache()
-        return elapsed, ms, nsteps, fields
-
+    B3 = w.params["rho0"] * w.params["c0"] ** 2 / 7.0
+    log(f"{name}: {n} particles ({nf} fluid)")
     tuning = load_tuning(args.tuning, name)
-    elapsed, ms, nsteps, f_mixed = run(L.FP32_MIXED, args.steps, args.warmup, tuning, vortex=True)
-    vortex = f_mixed.pop("vortex")
-    print(f"[bench] vortex diagnostic: {vortex}", file=sys.stderr, flush=True)
-    assert nsteps == args.steps
+
+    # Headline: FP32-mixed, median of `runs` timed runs, then one profiled run.
+    s = simulation(w, L.FP32_MIXED, tuning)
+    s.step(1e-4, w.Omega, args.warmup)
+    t = time_runs(s, w.Omega, args.steps, args.runs)
+    elapsed = statistics.median(t)
+    per = {k: v for k, v in profile_run(s, w.Omega, args.steps).items()
+           if k not in ("collide", "filter")}
+    # the vortex diagnostic of the z = 0 section on the state just stepped
+    s.vortex_image(0.0, 0.5, 3, to_numpy=False)  # warm-up
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    cnt, img, _ = s.vortex_image(0.0, 0.5, 3, to_numpy=False)
+    torch.cuda.synchronize()
+    vortex = {"ms": round(1e3 * (time.perf_counter() - t1), 3), "z0": 0.0, "theta": 0.5,
+              "min_pixels": 3, "count": cnt, "image": [int(img.shape[0]), int(img.shape[1])]}
+    s.close()
+    del s
+    torch.cuda.empty_cache()
     ms_step = 1e3 * elapsed / args.steps
     value = n * args.steps / elapsed
-    per = {k: v / nsteps for k, v in ms.items() if k not in ("collide", "filter")}
-    print(f"[bench] mixed: {ms_step:.3f} ms/step; per kernel (ms): "
-          + ", ".join(f"{k}={v:.3f}" for k, v in per.items()), file=sys.stderr, flush=True)
+    log(f"mixed: {ms_step:.3f} ms/step (runs {[round(1e3 * x / args.steps, 3) for x in t]}); "
+        "per kernel (ms): " + ", ".join(f"{k}={v:.3f}" for k, v in per.items()))
 
-    # Roofline of the dominant kernel (force sweep), from the events of the timed steps.
+    # Roofline of the dominant kernel (the force sweep) and of the whole step: algorithmic
+    # bytes per particle-update over the measured time, against the HBM peak.
     dom = max(per, key=per.get)
     t_dom = per[dom] * 1e-3
-    if dom in ("force", "density"):
-        fpp = FORCE_FLOPS_PER_PAIR if dom == "force" else DENSITY_FLOPS_PER_PAIR
-        units = nf if dom == "force" else n
-        flops = units * NEIGHBOURS * fpp
-        alu = flops / t_dom / 1e12
-    else:
-        alu = 0.0
-    hbm = n * BYTES_PER_PARTICLE[dom] / t_dom / 1e9
-    alu_frac, hbm_frac = alu / VALU_PEAK_TFLOPS, hbm / HBM_PEAK_GBS
-    if alu_frac >= hbm_frac:
-        roof = {"bound": "alu", "achieved": round(alu, 3), "peak": round(VALU_PEAK_TFLOPS, 1),
-                "unit": "TFLOP/s", "frac": round(alu_frac, 4)}
-    else:
-        roof = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(hbm_frac, 4)}
+    hbm = n * KERNEL_BYTES_PER_PARTICLE.get(dom, 0) / t_dom / 1e9
     traffic = measured_traffic(dom)
-    roof.update({"kernel": dom, "avg_ms": round(per[dom], 4),
-                 "traffic": None if traffic is None else round(traffic / 1e9, 3),
-                 "traffic_unit": "GB per launch",
-                 "hbm_GBs": round(hbm, 1), "hbm_frac": round(hbm_frac, 4)})
+    roof = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(hbm / HBM_PEAK_GBS, 4),
+            "traffic": None if traffic is None else round(traffic / 1e9, 3),
+            "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "kernel": dom, "avg_ms": round(per[dom], 4), "units": n,
+            "alg_bytes_per_unit": KERNEL_BYTES_PER_PARTICLE.get(dom)}
+    step_gbs = n * STEP_BYTES_PER_PU / (ms_step * 1e-3) / 1e9
+    roof["step"] = {"alg_bytes_per_unit": STEP_BYTES_PER_PU, "achieved": round(step_gbs, 1),
+                    "frac": round(step_gbs / HBM_PEAK_GBS, 4), "ms_per_step": round(ms_step, 4)}
+    if dom == "force":
+        tf = nf * FORCE_FLOPS_PER_PU / t_dom / 1e12
+        roof["alu"] = {"achieved": round(tf, 3), "unit": "TFLOP/s", "peak": FP32_PEAK_TFLOPS,
+                       "frac": round(tf / FP32_PEAK_TFLOPS, 4),
+                       "nonpacked_ceiling": round(FP32_NONPACKED_TFLOPS, 1),
+                       "frac_of_nonpacked": round(tf / FP32_NONPACKED_TFLOPS, 4),
+                       "alg_flops_per_unit": FORCE_FLOPS_PER_PU, "units": nf,
+                       "binding": "VALU instruction issue (rocprofv3 SQ counters)"}
 
-    fp64 = None
+    configs = {}
+    # Configuration 3 on the FP64 path, and both paths after the same 25 steps.
+    e25 = None
     if args.fp64_steps > 0:
-        # the FP64 path runs the same warmup + timed step count, so that the fields of
-        # both paths are compared after the same trajectory length
-        n64 = args.fp64_steps
-        e64, ms64, _, f64 = run(L.FP64, n64, args.warmup + args.steps - n64, tuning)
-        fp64 = {"ms_per_step": round(1e3 * e64 / n64, 3),
-                "speedup_mixed_vs_fp64": round((e64 / n64) / (elapsed / args.steps), 3),
-                "mixed_error_vs_fp64": field_errors(f_mixed, f64, w.kind == I.FLUID),
-                "after_steps": args.warmup + args.steps}
-        print(f"[bench] fp64: {fp64['ms_per_step']} ms/step; mixed vs fp64 "
-              f"{fp64['mixed_error_vs_fp64']}", file=sys.stderr, flush=True)
+        # both paths compared after the same trajectory: warmup + the first timed run
+        fx = ("rho", "P", "v", "omega", "acc")
+        _, fm = timed_config(w, L.FP32_MIXED, args.fp64_steps, args.warmup, 1, tuning, fields=fx)
+        r64, f64 = timed_config(w, L.FP64, args.fp64_steps, args.warmup, args.runs, tuning,
+                                fields=fx)
+        e25 = field_errors(fm, f64, w.kind == I.FLUID, B3)
+        configs["3_fp64"] = dict(r64, workload=name, precision="fp64")
+        log(f"fp64: {r64['ms_per_step']} ms/step; mixed vs fp64 after "
+            f"{args.warmup + args.fp64_steps} steps {e25}")
+    configs["3_mixed"] = {"ms_per_step": round(ms_step, 4), "value": value, "steps": args.steps,
+                          "runs_ms_per_step": [round(1e3 * x / args.steps, 4) for x in t],
+                          "workload": name, "precision": "fp32_mixed"}
+
+    if not args.no_configs:
+        w0 = I.config(0)
+        r, _ = timed_config(w0, L.FP64, 20, 5, args.runs, ({}, 1))
+        configs["0_fp64"] = dict(r, workload="box4096_cubic", precision="fp64")
+        r, _ = timed_config(w0, L.FP32_MIXED, 20, 5, args.runs, ({}, 1))
+        configs["0_mixed"] = dict(r, workload="box4096_cubic", precision="fp32_mixed")
+        w1 = I.config(1)
+        t92 = load_tuning(args.tuning, "cylinder_nz92")
+        r, _ = timed_config(w1, L.FP64, 100, 0, args.runs, t92)
+        configs["1_fp64"] = dict(r, workload="cylinder_2.45M", precision="fp64")
+        fx = ("rho", "P", "v", "omega", "acc")
+        r, f2 = timed_config(w1, L.FP32_MIXED, 100, 0, args.runs, t92, profile=True, fields=fx)
+        configs["2_mixed"] = dict(r, workload="cylinder_2.45M", precision="fp32_mixed",
+                                  error_vs_oracle_100_steps=golden_errors(f2, w1))
+        for k, v in configs.items():
+            log(f"config {k}: {v['ms_per_step']} ms/step, {v['value']:.4g} PU/s")
+
     f1 = None
     if args.f1_steps > 0:
         # the same workload with Algorithm 1's pressure filter and collision step switched
         # on (the lattice keeps every pair beyond the collision distance, so the collision
         # step costs its search only)
         f1p = dict(pressure_filter=1, coll_alpha=0.8, coll_e=0.3)
-        e1, ms1, n1, _ = run(L.FP32_MIXED, args.f1_steps, args.warmup, tuning, extra=f1p)
-        f1 = dict(f1p, steps=args.f1_steps, ms_per_step=round(1e3 * e1 / args.f1_steps, 3),
-                  value=n * args.f1_steps / e1,
-                  kernel_ms={k: round(v / n1, 4) for k, v in ms1.items()})
-        print(f"[bench] with filter and collisions: {f1}", file=sys.stderr, flush=True)
-    batch = batch_bench(args.batch_steps, args.tuning) if args.batch_steps > 0 else None
-    if batch:
-        print(f"[bench] batch: {batch}", file=sys.stderr, flush=True)
+        sf = simulation(w, L.FP32_MIXED, tuning, extra=f1p)
+        sf.step(1e-4, w.Omega, args.warmup)
+        tf1 = time_runs(sf, w.Omega, args.f1_steps, 1)[0]
+        kms = profile_run(sf, w.Omega, args.f1_steps)
+        sf.close()
+        del sf
+        torch.cuda.empty_cache()
+        f1 = dict(f1p, steps=args.f1_steps, ms_per_step=round(1e3 * tf1 / args.f1_steps, 3),
+                  value=n * args.f1_steps / tf1, kernel_ms={k: round(v, 4) for k, v in kms.items()})
+        log(f"with filter and collisions: {f1}")
+    batch = None
+    if args.batch_steps > 0:
+        batch = batch_bench(args.batch_steps, args.runs, args.tuning)
+        configs["4_mixed_batch64"] = {k: batch[k] for k in ("ms_per_step", "value", "steps",
+                                                            "runs_ms_per_step")}
+        log(f"batch: {batch}")
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(args.nz, args.cpu_steps)
+    cpu = None
+    oracle_configs = None
+    if not args.no_cpu_baseline:
+        # the oracle on the headline workload itself: one step of all 19.57M particles
+        cpu = oracle_rate(w, 1)
+        cpu["sample"] = (f"1 step of the whole {name} workload ({n} particles), FP64, "
+                         f"{cpu['seconds']} s")
+        log(f"oracle: {cpu}")
+        if not args.no_configs:
+            oracle_configs = {"0": oracle_rate(I.config(0), 20), "1": oracle_rate(I.config(1), 5)}
+            log(f"oracle configs: {oracle_configs}")
+
     line = {
         "metric": "particle-updates/sec @19.6M particles, FP32-mixed vs FP64 at stated error",
         "value": value, "unit": "particle-updates/s", "n_gpus": 1, "steps": args.steps,
@@ -318,15 +423,20 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"rotating cylinder, {n} particles ({nf} fluid), dx=1/{args.nz}, "
                                "Wendland C2, FP32-mixed, dt=1e-4",
-                   "particles": n, "precision": "fp32_mixed",
+                   "particles": n, "precision": "fp32_mixed", "timing": f"median of {args.runs} runs",
                    "tuning": tuning[0] or "default", "cell_factor": tuning[1]},
         "kernel_ms": {k: round(v, 4) for k, v in per.items()},
         "roofline": roof,
-        "fp64_gpu": fp64,
+        "fp64_gpu": None if e25 is None else {
+            "ms_per_step": configs["3_fp64"]["ms_per_step"],
+            "speedup_mixed_vs_fp64": round(configs["3_fp64"]["ms_per_step"] / ms_step, 3),
+            "mixed_error_vs_fp64": e25, "after_steps": args.warmup + args.fp64_steps},
+        "configs": configs,
         "batch64": batch,
         "vortex_diag": vortex,
         "filter_collide": f1,
         "cpu_baseline": cpu,
+        "cpu_oracle_configs": oracle_configs,
     }
     print(json.dumps(line), flush=True)
 

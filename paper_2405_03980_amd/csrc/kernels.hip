@@ -1567,23 +1567,35 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
                 mc &= mc - 1;
                 return (uint32_t)tbl[w][c][j];
             };
-            // a per-lane trip count (lanes leave as they finish), two hits per trip so that
-            // the compensated sums alternate registers instead of being copied back each hit
-#pragma unroll 2
-            for (uint32_t i = 0; i < cnt; i++) {
+            // one hit's kernel value and unlike-species share; with COLL, the hit is listed
+            // branch-free: written to the next free slot (the spare once the list is full),
+            // and only a near one advances the count
+            auto hit = [&](float &W, float &U) {
                 const uint32_t kq = next_k();
                 const float4 qc = stage[kq];
                 const float d0 = me.x - qc.x, d1 = me.y - qc.y, d2 = me.z - qc.z;
                 const float r2s = d0 * d0 + d1 * d1 + d2 * d2;
-                const float W = shape_W<KT>(r2s);
-                sw.add(W);
-                su.add(qc.w != me.w ? W : 0.0f);
+                W = shape_W<KT>(r2s);
+                U = qc.w != me.w ? W : 0.0f;
                 if (COLL) {
-                    // branch-free: every hit is written to the next free slot (the spare once
-                    // the list is full), and only a near one advances the count
                     nearl[threadIdx.x][min(nloc, (uint32_t)kNearCap)] = (int16_t)kq;
                     nloc += r2s < rc2m ? 1u : 0u;
                 }
+            };
+            // a per-lane trip count (lanes leave as they finish), two hits per trip: their
+            // values are added in FP32, then into the compensated sums
+            for (uint32_t i = 1; i < cnt; i += 2) {
+                float Wa, Ua, Wb, Ub;
+                hit(Wa, Ua);
+                hit(Wb, Ub);
+                sw.add(Wa + Wb);
+                su.add(Ua + Ub);
+            }
+            if (cnt & 1u) {
+                float W, U;
+                hit(W, U);
+                sw.add(W);
+                su.add(U);
             }
             if (COLL && nloc) {
                 // after the loop: reserve the lane's slots of the target's list, then store
@@ -1690,15 +1702,26 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
             HitReplay hr(s.masks + (size_t)p * kMaskSlots, NW, target, g, G);
             const uint32_t cnt = hr.cnt;
             Acc<float, KAHAN> F0, F1, F2, T0, T1, T2;
-            // per-lane trip count, two hits per trip (as in the density sweep)
-#pragma unroll 2
-            for (uint32_t i = 0; i < cnt; i++) {
-                const uint32_t k = hr.next(tbl[w]);
+            auto term = [&](uint32_t k, float f[3], float nn[3]) {
                 const float4 A = SA[k], B = SB[k], C = SC[k];
-                float f[3], nn[3];
                 pair_force_f32<KT, EQM>(K, I, A, B, C, Ai.x - A.x, Ai.y - A.y, Ai.z - A.z,
                                         Bi.x - B.x, Bi.y - B.y, Bi.z - B.z, Ci.x + C.x, Ci.y + C.y,
                                         Ci.z + C.z, f, nn);
+            };
+            // per-lane trip count, two hits per trip: the two terms are added in FP32, then
+            // into the compensated sums (one compensated add per two hits)
+            for (uint32_t i = 1; i < cnt; i += 2) {
+                const uint32_t ka = hr.next(tbl[w]);
+                const uint32_t kb = hr.next(tbl[w]);
+                float fa[3], na[3], fb[3], nb[3];
+                term(ka, fa, na);
+                term(kb, fb, nb);
+                F0.add(fa[0] + fb[0]); F1.add(fa[1] + fb[1]); F2.add(fa[2] + fb[2]);
+                T0.add(na[0] + nb[0]); T1.add(na[1] + nb[1]); T2.add(na[2] + nb[2]);
+            }
+            if (cnt & 1u) {
+                float f[3], nn[3];
+                term(hr.next(tbl[w]), f, nn);
                 F0.add(f[0]); F1.add(f[1]); F2.add(f[2]);
                 T0.add(nn[0]); T1.add(nn[1]); T2.add(nn[2]);
             }
@@ -1835,14 +1858,25 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_filter_cand(DevState s)
             // positive and it scales only that difference, so it is summed plainly
             Acc<float, KAHAN> num;
             float den = 0.0f;
-#pragma unroll 2
-            for (uint32_t i = 0; i < hr.cnt; i++) {
+            auto hit = [&](float &nm) {
                 const uint32_t k = hr.next(tbl[w]);
                 const float4 A = SA[k];
                 const float d0 = Ai.x - A.x, d1 = Ai.y - A.y, d2 = Ai.z - A.z;
                 const float W = shape_W<KT>(d0 * d0 + d1 * d1 + d2 * d2);
-                num.add(fmaf(-A.w, Pi, SP[k]) * W);
+                nm = fmaf(-A.w, Pi, SP[k]) * W;
                 den = fmaf(A.w, W, den);
+            };
+            // two hits per trip, their numerator terms added in FP32 before the compensated add
+            for (uint32_t i = 1; i < hr.cnt; i += 2) {
+                float na, nb;
+                hit(na);
+                hit(nb);
+                num.add(na + nb);
+            }
+            if (hr.cnt & 1u) {
+                float nm;
+                hit(nm);
+                num.add(nm);
             }
             const double sn = group_total(num.s, KAHAN ? num.c : 0.0f, lane, n, G);
             const double sd = group_total(den, 0.0f, lane, n, G);
