@@ -51,7 +51,8 @@ KERNEL_BYTES_PER_PARTICLE = {
     "force": FORCE_BYTES_PER_PU,
 }
 GOLD100 = os.path.join(ROOT, "tests", "golden", "cylinder_2p45M_100steps.npz")
-TUNING_KEYS = ("block_density", "block_force", "block_stream", "use_graph", "sweep")
+TUNING_KEYS = ("block_density", "block_force", "block_stream", "use_graph", "sweep", "xcd_run",
+        "list_targets")
 
 
 def parse():

@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define SPH_ABI_VERSION 2u
+#define SPH_ABI_VERSION 3u
 
 typedef enum {
     SPH_OK = 0,
@@ -126,6 +126,10 @@ typedef struct {
                             /* LDS, lanes over candidates for the neighbour test; needs    */
                             /* cell_factor 1 on every instance (else 1 is used); 0: keep;  */
                             /* any other value is SPH_E_INVALID                            */
+    int32_t xcd_run;        /* brick sweeps: consecutive bricks (in Morton order) given to   */
+                            /* each of the 8 XCDs in turn, 1..256 (default 16); 0: keep      */
+    int32_t list_targets;   /* brick density sweep: targets tested per round, 16 or 32        */
+                            /* (default 32); 0: keep                                          */
 } sph_tuning;
 
 typedef struct sph_sim sph_sim;      /* one SPH instance (opaque, host memory)            */

@@ -11,7 +11,7 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libsph4he.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 OK, E_INVALID, E_WORKSPACE, E_HIP, E_STATE, E_DOMAIN, E_NONFINITE, E_UNSUPPORTED, E_CAPACITY = range(9)
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_WORKSPACE", 3: "E_HIP", 4: "E_STATE",
@@ -39,7 +39,8 @@ class SphParams(C.Structure):
 
 class SphTuning(C.Structure):
     _fields_ = [("block_density", C.c_int32), ("block_force", C.c_int32),
-                ("block_stream", C.c_int32), ("use_graph", C.c_int32), ("sweep", C.c_int32)]
+                ("block_stream", C.c_int32), ("use_graph", C.c_int32), ("sweep", C.c_int32),
+                ("xcd_run", C.c_int32), ("list_targets", C.c_int32)]
 
 
 # name -> (restype, argtypes)

@@ -1274,7 +1274,7 @@ __device__ __forceinline__ void pair_force_f32(const PairK &k, const PairI &I, f
 // G equal consecutive shares of the target's hits in list order.
 
 constexpr int kCandWin = 10;      // windows per wave: stencils of up to 640 candidates
-constexpr int kListTargets = 32;  // targets per round of the density sweep (masks in LDS)
+constexpr int kListTargets = 32;  // largest number of targets per round of the density sweep
 static_assert(kCandWin <= kMaskSlots, "a target's masks must fit its mask slots");
 static_assert(kStageDensity <= 32767 && kStageForce <= 32767, "staged indices are int16");
 
@@ -1316,13 +1316,14 @@ __device__ __forceinline__ uint32_t stencil_self(const StencilList &S, uint32_t 
 }
 
 // Workgroups are dealt to the XCDs in turn (workgroup i runs on XCD i mod kXcd).  Giving
-// each XCD runs of kXcdRun consecutive bricks of the Morton order makes the neighbourhoods
-// that its resident workgroups stage overlap, so more staging loads hit that XCD's own L2,
-// while the runs stay short enough to spread uneven work over all XCDs.
-constexpr uint32_t kXcd = 8, kXcdRun = 16;
-__device__ __forceinline__ uint32_t brick_of_workgroup(uint32_t wg, uint32_t nb)
+// each XCD runs of `run` consecutive bricks of the Morton order (a tuning parameter, 1..256)
+// makes the neighbourhoods that its resident workgroups stage overlap, so more staging
+// loads hit that XCD's own L2, while the runs stay short enough to spread uneven work over
+// all XCDs.
+constexpr uint32_t kXcd = 8;
+__device__ __forceinline__ uint32_t brick_of_workgroup(uint32_t wg, uint32_t nb, uint32_t run)
 {
-    const uint32_t P = kXcd * kXcdRun, base = wg / P * P, T = min(P, nb - base), in = wg - base;
+    const uint32_t P = kXcd * run, base = wg / P * P, T = min(P, nb - base), in = wg - base;
     const uint32_t q = T / kXcd, r = T % kXcd, x = in % kXcd;
     return base + x * q + min(x, r) + in / kXcd;
 }
@@ -1440,17 +1441,18 @@ __device__ __forceinline__ void test_targets(const float4 *stage, const float *p
 // the collision step tests only those, exactly.  Targets with more, targets evaluated per
 // particle (fallbacks) and collision distances near 2h get kNearOverflow: the collision
 // step walks their cells.
-template <bool KAHAN, bool COLL>
+template <bool KAHAN, bool COLL, int LT>
 __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
 {
+    static_assert(LT >= 1 && LT <= kListTargets, "targets per round");
     __shared__ BrickFrame F;
     __shared__ float4 stage[kStageDensity];
     __shared__ int16_t tbl[kBrickThreads / 64][kCandWin][64];
-    __shared__ uint64_t msk[kBrickThreads / 64][kListTargets][kCandWin];
-    __shared__ uint32_t ncnt[kBrickThreads / 64][kListTargets];  // near neighbours listed (COLL)
+    __shared__ uint64_t msk[kBrickThreads / 64][LT][kCandWin];
+    __shared__ uint32_t ncnt[kBrickThreads / 64][LT];  // near neighbours listed (COLL)
     __shared__ int16_t nearl[kBrickThreads][kNearCap + 1];        // a lane's near hits (COLL;
                                                                   // the last is a spare)
-    const uint32_t brick = brick_of_workgroup(blockIdx.x, gridDim.x);
+    const uint32_t brick = brick_of_workgroup(blockIdx.x, gridDim.x, s.xcd_run);
     const uint32_t bxyz = s.brick_xyz[brick];
     const InstDesc *d = s.desc + s.brick_inst[brick];
     const uint8_t *SK = s.sk[s.cur];
@@ -1507,8 +1509,8 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
     // compiled once per smoothing kernel, chosen per brick (as in the force sweep)
     auto sweep = [&](auto kt) {
         constexpr int KT = decltype(kt)::value;
-        for (uint32_t t0 = 0; t0 < nt; t0 += kListTargets) {
-            const uint32_t ntc = min((uint32_t)kListTargets, nt - t0);
+        for (uint32_t t0 = 0; t0 < nt; t0 += LT) {
+            const uint32_t ntc = min((uint32_t)LT, nt - t0);
             // test: one target at a time against every window; lane t collects target t's
             // masks
             uint64_t mw[kCandWin];
@@ -1639,7 +1641,7 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
     __shared__ float4 SC[kStageForce];   // half the spin, V/S
     __shared__ double vref[3];
     __shared__ int16_t tbl[kBrickThreads / 64][kCandWin][64];
-    const uint32_t brick = brick_of_workgroup(blockIdx.x, gridDim.x);
+    const uint32_t brick = brick_of_workgroup(blockIdx.x, gridDim.x, s.xcd_run);
     const uint32_t bxyz = s.brick_xyz[brick];
     const InstDesc *d = s.desc + s.brick_inst[brick];
     const uint8_t *SK = s.sk[s.cur];
@@ -1795,7 +1797,7 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_filter_cand(DevState s)
     __shared__ float4 SA[kStageForce];  // position (brick frame), source volume
     __shared__ float SP[kStageForce];   // source volume times pressure
     __shared__ int16_t tbl[kBrickThreads / 64][kCandWin][64];
-    const uint32_t brick = brick_of_workgroup(blockIdx.x, gridDim.x);
+    const uint32_t brick = brick_of_workgroup(blockIdx.x, gridDim.x, s.xcd_run);
     const uint32_t bxyz = s.brick_xyz[brick];
     const InstDesc *d = s.desc + s.brick_inst[brick];
     if (!d->pfilter) return;  // the same for the whole workgroup
@@ -2326,7 +2328,7 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_vortex_cand(DevState s, Vo
     __shared__ float4 SA[kStageForce];  // position (brick frame), V of a viscous particle
     __shared__ float4 SW[kStageForce];  // spin at the end of the step
     __shared__ int16_t tbl[kBrickThreads / 64][kCandWin][64];
-    const uint32_t brick = brick_of_workgroup(blockIdx.x, gridDim.x);
+    const uint32_t brick = brick_of_workgroup(blockIdx.x, gridDim.x, s.xcd_run);
     const uint32_t bxyz = s.brick_xyz[brick];
     const InstDesc *d = s.desc + s.brick_inst[brick];
     {
@@ -2524,8 +2526,13 @@ hipError_t launch_density(const DevState &d, const Launch &L, hipStream_t st)
     if (d.precision == 0) k_density<double, false><<<g, L.bs_density, 0, st>>>(d);
     else if (L.sweep == SWEEP_CAND && d.n_bricks) {
         k_brick_frames<<<d.n_bricks, 64, 0, st>>>(d);
-        if (d.any_coll) k_density_cand<true, true><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
-        else k_density_cand<true, false><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
+        if (L.list_targets == 16) {
+            if (d.any_coll) k_density_cand<true, true, 16><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
+            else k_density_cand<true, false, 16><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
+        } else {
+            if (d.any_coll) k_density_cand<true, true, 32><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
+            else k_density_cand<true, false, 32><<<d.n_bricks, kBrickThreads, 0, st>>>(d);
+        }
     }
     else k_density<float, true><<<g, L.bs_density, 0, st>>>(d);
     return hipGetLastError();

@@ -669,6 +669,7 @@ sph_status sph_batch_create(int32_t n_inst, const sph_params *params, const int6
     b->ds.n_waves = pl.n_waves;
     b->ds.any_filter = pl.any_filter ? 1 : 0;
     b->ds.any_coll = pl.any_coll ? 1 : 0;
+    b->ds.xcd_run = kDefaultXcdRun;
     std::vector<uint32_t> rank_of_lin, xyz, bxyz, binst;
     cell_tables(pl, rank_of_lin, xyz);
     brick_tables(pl, bxyz, binst);
@@ -751,6 +752,13 @@ sph_status sph_batch_set_tuning(sph_batch *b, const sph_tuning *t)
         b->err = "sweep must be 0 (keep), 1 (per particle) or 3 (brick, candidate ballots)";
         return SPH_E_INVALID;
     }
+    if (t->xcd_run < 0 || t->xcd_run > 256) { b->err = "xcd_run must be in 0..256"; return SPH_E_INVALID; }
+    if (t->list_targets != 0 && t->list_targets != 16 && t->list_targets != 32) {
+        b->err = "list_targets must be 0 (keep), 16 or 32";
+        return SPH_E_INVALID;
+    }
+    if (t->xcd_run) b->ds.xcd_run = (uint32_t)t->xcd_run;
+    if (t->list_targets) b->L.list_targets = t->list_targets;
     if (t->sweep) b->L.sweep = t->sweep;
     if (t->block_density) b->L.bs_density = t->block_density;
     if (t->block_force) b->L.bs_force = t->block_force;
@@ -960,6 +968,8 @@ sph_status sph_get_tuning(const sph_sim *s, sph_tuning *t)
     t->block_stream = s->b->L.bs_stream;
     t->use_graph = s->b->use_graph ? 1 : 0;
     t->sweep = s->b->L.sweep;
+    t->xcd_run = (int32_t)s->b->ds.xcd_run;
+    t->list_targets = s->b->L.list_targets;
     return SPH_OK;
 }
 

@@ -83,6 +83,7 @@ struct DevState {
     // records the windows of candidate tests, the pressure filter and the force sweep
     // replay them.
     uint64_t *masks;
+    uint32_t xcd_run;  // consecutive bricks per XCD in the brick sweeps' workgroup order
 };
 
 constexpr int kMaskSlots = 16;
@@ -98,7 +99,9 @@ enum { SWEEP_THREAD = 1, SWEEP_CAND = 3 };
 struct Launch {
     int bs_density = 256, bs_force = 256, bs_stream = 256;
     int sweep = SWEEP_CAND;  // brick sweeps when every instance allows them (FP32-mixed, cf = 1)
+    int list_targets = 32;   // targets per round of the brick density sweep: 16 or 32
 };
+constexpr uint32_t kDefaultXcdRun = 16;
 
 // Launchers (kernels.hip).  All enqueue on `st` and return hipGetLastError().
 // mode 0: load/initial evaluation (no kick or drift); mode 1: time step.

@@ -196,8 +196,10 @@ class Simulation:
             return int(cnt.value), img.cpu().numpy(), lab.cpu().numpy()
         return int(cnt.value), img, lab
 
-    def set_tuning(self, block_density=0, block_force=0, block_stream=0, use_graph=-1, sweep=0):
-        t = L.SphTuning(block_density, block_force, block_stream, use_graph, sweep)
+    def set_tuning(self, block_density=0, block_force=0, block_stream=0, use_graph=-1, sweep=0,
+                   xcd_run=0, list_targets=0):
+        t = L.SphTuning(block_density, block_force, block_stream, use_graph, sweep, xcd_run,
+                        list_targets)
         _check(self.lib.sph_set_tuning(self._h, C.byref(t)), "sph_set_tuning", self._err)
 
     def profile_begin(self):
@@ -214,7 +216,8 @@ class Simulation:
         t = L.SphTuning()
         _check(self.lib.sph_get_tuning(self._h, C.byref(t)), "sph_get_tuning", self._err)
         return dict(block_density=t.block_density, block_force=t.block_force,
-                    block_stream=t.block_stream, use_graph=t.use_graph, sweep=t.sweep)
+                    block_stream=t.block_stream, use_graph=t.use_graph, sweep=t.sweep,
+                    xcd_run=t.xcd_run, list_targets=t.list_targets)
 
 
 class Batch:
@@ -301,8 +304,10 @@ class Batch:
         _check(self.lib.sph_batch_diagnostics(self._h, out), "sph_batch_diagnostics", self._err)
         return np.array(out[:]).reshape(self.n_inst, 7)
 
-    def set_tuning(self, block_density=0, block_force=0, block_stream=0, use_graph=-1, sweep=0):
-        t = L.SphTuning(block_density, block_force, block_stream, use_graph, sweep)
+    def set_tuning(self, block_density=0, block_force=0, block_stream=0, use_graph=-1, sweep=0,
+                   xcd_run=0, list_targets=0):
+        t = L.SphTuning(block_density, block_force, block_stream, use_graph, sweep, xcd_run,
+                        list_targets)
         _check(self.lib.sph_batch_set_tuning(self._h, C.byref(t)), "sph_batch_set_tuning", self._err)
 
     def profile_begin(self):

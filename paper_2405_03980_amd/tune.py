@@ -1,5 +1,6 @@
 """Autotuner of the launch shape: sweep implementation, cells per interaction radius,
-block sizes and graph replay, picked by timing a few steps of the real workload.
+brick-sweep tiling (bricks per XCD run, targets per density round), block sizes and graph
+replay, picked by timing a few steps of the real workload.
 
 Results are cached as JSON ({workload name: settings}) and read by bench.py.  The
 settings change performance only: every candidate computes the same method (the cell
@@ -22,38 +23,49 @@ from . import inputs as I
 
 
 def candidates(batch: bool):
-    """Settings to try: the brick sweeps (cell factor 1) with a few streaming block sizes,
-    and per-particle sweeps for cell factors 1 and 2 over block sizes."""
+    """Settings to try: the brick sweeps (cell factor 1) over the bricks given to each XCD in
+    a run, the targets per density round, streaming block sizes and graph replay; and the
+    per-particle sweeps for cell factors 1 and 2 over block sizes."""
     out = []
-    for bs in (128, 256, 512):
+    for run, lt, bs in itertools.product((4, 8, 16, 32, 64), (16, 32), (256, 512)):
         for graph in ((1,) if batch else (0, 1)):
-            out.append(dict(cell_factor=1, sweep=3, block_stream=bs, use_graph=graph))
-    for cf, bd, bf in itertools.product((1, 2), (128, 256), (64, 128, 256)):
+            out.append(dict(cell_factor=1, sweep=3, xcd_run=run, list_targets=lt, block_stream=bs,
+                            use_graph=graph))
+    for cf, bd, bf in itertools.product((1, 2), (128, 256), (128, 256)):
         out.append(dict(cell_factor=cf, sweep=1, block_density=bd, block_force=bf,
                         block_stream=256, use_graph=1))
     return out
 
 
 def _time_single(w, cand, steps):
-    import torch
     from . import sim as S
     params = dict(w.params, cell_factor=cand["cell_factor"])
     s = S.Simulation(params, w.n, precision=L.FP32_MIXED)
     s.init(w.x, w.v, w.omega, w.species, w.kind)
     s.set_tuning(**{k: v for k, v in cand.items() if k != "cell_factor"})
-    s.step(1e-4, w.Omega, 2)
-    s.sync()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.step(1e-4, w.Omega, steps)
-    s.sync()
-    dt = (time.perf_counter() - t0) / steps
+    dt = _timed(s, w.Omega, steps)
     s.close()
     return dt
 
 
-def _time_batch(ws, cand, steps):
+def _timed(obj, Om, steps):
+    """Seconds per step: warm-up calls that also capture the step graphs of both buffer
+    parities, then the better of two timed calls of `steps` steps."""
     import torch
+    for _ in range(2):
+        obj.step(1e-4, Om, 3)
+    best = float("inf")
+    for _ in range(2):
+        obj.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        obj.step(1e-4, Om, steps)
+        obj.sync()
+        best = min(best, (time.perf_counter() - t0) / steps)
+    return best
+
+
+def _time_batch(ws, cand, steps):
     from . import sim as S
     import numpy as np
     params = [dict(w.params, cell_factor=cand["cell_factor"]) for w in ws]
@@ -62,19 +74,12 @@ def _time_batch(ws, cand, steps):
            np.concatenate([w.omega for w in ws], axis=1), np.concatenate([w.species for w in ws]),
            np.concatenate([w.kind for w in ws]))
     b.set_tuning(**{k: v for k, v in cand.items() if k != "cell_factor"})
-    Om = [w.Omega for w in ws]
-    b.step(1e-4, Om, 2)
-    b.sync()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.step(1e-4, Om, steps)
-    b.sync()
-    dt = (time.perf_counter() - t0) / steps
+    dt = _timed(b, [w.Omega for w in ws], steps)
     b.close()
     return dt
 
 
-def tune(kind: str, nz: int = 184, steps: int = 4, log=sys.stderr) -> tuple[str, dict, list]:
+def tune(kind: str, nz: int = 184, steps: int = 6, log=sys.stderr) -> tuple[str, dict, list]:
     if kind == "batch":
         ws = I.make_batch(64)
         name = "batch64"
@@ -102,7 +107,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", choices=("cylinder", "batch"), default="cylinder")
     ap.add_argument("--nz", type=int, default=184)
-    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "tuned.json"))
     a = ap.parse_args()
     name, best, _ = tune(a.workload, a.nz, a.steps)

@@ -22,7 +22,8 @@ from tests._parity import field_errors, positions_ok
 pytestmark = pytest.mark.gpu
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KEYS = ("block_density", "block_force", "block_stream", "use_graph", "sweep")
+KEYS = ("block_density", "block_force", "block_stream", "use_graph", "sweep", "xcd_run",
+        "list_targets")
 
 
 def _tuned(name):
