@@ -1632,6 +1632,11 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
     if (err) atomicOr(s.err, err);
 }
 
+// The fluid targets of a brick, in cell order, are dealt to its eight waves in equal
+// contiguous shares, so that the waves finish together whatever the cells' populations (a
+// workgroup holds its LDS until its last wave ends, and on a lattice the cells of one brick
+// hold 8 to 27 particles).  Each wave builds its own cell's stencil list first; a target
+// then replays its masks through the list of its own cell.
 template <bool KAHAN>
 __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
 {
@@ -1641,6 +1646,8 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
     __shared__ float4 SC[kStageForce];   // half the spin, V/S
     __shared__ double vref[3];
     __shared__ int16_t tbl[kBrickThreads / 64][kCandWin][64];
+    __shared__ uint64_t tmask[kBrickThreads / 64];  // fluid targets of each cell
+    __shared__ int32_t cellnw[kBrickThreads / 64];  // windows of each cell's stencil list
     const uint32_t brick = brick_of_workgroup(blockIdx.x, gridDim.x, s.xcd_run);
     const uint32_t bxyz = s.brick_xyz[brick];
     const InstDesc *d = s.desc + s.brick_inst[brick];
@@ -1661,60 +1668,83 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
     }
     stage_force(s, F, M, vref, d->inv_h, SA, SB, SC);
     __syncthreads();
-    if (!has_cell) return;
-    const uint32_t toff = F.off[tslot], pbase = F.begin[tslot];
-    const uint32_t nt = F.off[tslot + 1] - toff;
-    if (nt == 0) return;
-    const StencilList S = stencil_list(F, ts, lane, &tbl[w][0][0]);
-    if (S.NW > (uint32_t)kCandWin) {
-        for (uint32_t i = lane; i < nt; i += 64) err |= force_one<float, KAHAN>(s, d, pbase + i);
-        if (err) atomicOr(s.err, err);
-        return;
+    // Cell w: its stencil list and fluid targets; wall targets are finished here (zero force
+    // and torque), and a cell of more than 64 particles or a stencil longer than the windows
+    // is evaluated per particle by its wave.
+    {
+        const uint32_t toff = F.off[tslot], pbase = F.begin[tslot];
+        const uint32_t nt = has_cell ? F.off[tslot + 1] - toff : 0u;
+        uint64_t fl = 0;
+        int nw = 0;
+        if (nt) {
+            const StencilList S = stencil_list(F, ts, lane, &tbl[w][0][0]);
+            if (S.NW > (uint32_t)kCandWin || nt > 64u) {
+                for (uint32_t i = lane; i < nt; i += 64) err |= force_one<float, KAHAN>(s, d, pbase + i);
+            } else {
+                nw = (int)S.NW;
+                uint32_t sk_t = 0;
+                if ((uint32_t)lane < nt) sk_t = SK[pbase + lane];
+                const bool fluid = (uint32_t)lane < nt && (sk_t >> 1) == KIND_FLUID;
+                if ((uint32_t)lane < nt && !fluid) {
+                    const double z[3] = {0.0, 0.0, 0.0};
+                    err |= force_finish<float>(s, d, pbase + lane, sk_t & 1, z, z);
+                }
+                fl = __ballot(fluid);
+            }
+        }
+        if (lane == 0) {
+            tmask[w] = fl;
+            cellnw[w] = nw;
+        }
     }
+    __syncthreads();
+    uint32_t T = 0;
+    for (int c = 0; c < 8; c++) T += (uint32_t)__popcll(tmask[c]);
+    const uint32_t b0 = (T * (uint32_t)w) / 8u, b1 = (T * (uint32_t)(w + 1)) / 8u;
     const PairK K(d);
     const double th = -0.5 * d->h;  // torque = -(h/2) n'
-    const int NW = (int)S.NW;
-    // Per block of up to 64 targets: wall targets get zero force and torque directly, and the
-    // fluid targets share the lanes as (target, group g of G), so walls take no lanes.
-    // Compiled once per smoothing kernel and for equal or unequal species masses, chosen
-    // per brick (a batch may mix them), so that the hit loop carries no branch on them.
+    // Per block of up to 64 of the wave's targets: they share the lanes as (target, group g
+    // of G).  Compiled once per smoothing kernel and for equal or unequal species masses,
+    // chosen per brick (a batch may mix them), so that the hit loop carries no branch on them.
     auto sweep = [&](auto kt, auto eqm) {
         constexpr int KT = decltype(kt)::value;
         constexpr bool EQM = decltype(eqm)::value;
-        for (uint32_t t0 = 0; t0 < nt; t0 += 64) {
-            const uint32_t nb = min(64u, nt - t0);
-            uint32_t sk_t = 0;
-            if ((uint32_t)lane < nb) sk_t = SK[pbase + t0 + lane];
-            const bool fluid_t = (uint32_t)lane < nb && (sk_t >> 1) == KIND_FLUID;
-            const uint64_t M = __ballot(fluid_t);
-            if ((uint32_t)lane < nb && !fluid_t) {
-                const double z[3] = {0.0, 0.0, 0.0};
-                err |= force_finish<float>(s, d, pbase + t0 + lane, sk_t & 1, z, z);
-            }
-            if (M == 0) continue;
-            const int n = __popcll(M);
+        for (uint32_t f0 = b0; f0 < b1; f0 += 64) {
+            const int n = (int)min(64u, b1 - f0);
             const int G = 64 / n;
             const int g = lane / n;
             const bool target = g < G;
-            const uint32_t t = (uint32_t)__builtin_ctzll(drop_low_bits(M, (uint32_t)(lane % n)));
-            const uint32_t p = pbase + t0 + t;
-            const uint32_t ki = toff + t0 + t;
+            // this lane's target: flat index f, the rank-th fluid target of cell c
+            const uint32_t f = f0 + (uint32_t)(lane % n);
+            int c = 0;
+            uint32_t rank = 0, before = 0;
+            for (int cc = 0; cc < 8; cc++) {
+                if (f >= before) {
+                    c = cc;
+                    rank = f - before;
+                }
+                before += (uint32_t)__popcll(tmask[cc]);
+            }
+            const uint32_t local = (uint32_t)__builtin_ctzll(drop_low_bits(tmask[c], rank));
+            const int cs = slot_index(1 + (c & 1), 1 + ((c >> 1) & 1), 1 + (c >> 2));
+            const uint32_t p = F.begin[cs] + local;
+            const uint32_t ki = F.off[cs] + local;
             const float4 Ai = SA[ki], Bi = SB[ki], Ci = SC[ki];
             const PairI I = pair_target(K, Ai, Bi, Ci);
-            HitReplay hr(s.masks + (size_t)p * kMaskSlots, NW, target, g, G);
+            HitReplay hr(s.masks + (size_t)p * kMaskSlots, cellnw[c], target, g, G);
             const uint32_t cnt = hr.cnt;
             Acc<float, KAHAN> F0, F1, F2, T0, T1, T2;
-            auto term = [&](uint32_t k, float f[3], float nn[3]) {
+            auto term = [&](uint32_t k, float fo[3], float nn[3]) {
                 const float4 A = SA[k], B = SB[k], C = SC[k];
                 pair_force_f32<KT, EQM>(K, I, A, B, C, Ai.x - A.x, Ai.y - A.y, Ai.z - A.z,
                                         Bi.x - B.x, Bi.y - B.y, Bi.z - B.z, Ci.x + C.x, Ci.y + C.y,
-                                        Ci.z + C.z, f, nn);
+                                        Ci.z + C.z, fo, nn);
             };
             // per-lane trip count, two hits per trip: the two terms are added in FP32, then
             // into the compensated sums (one compensated add per two hits)
             for (uint32_t i = 1; i < cnt; i += 2) {
-                const uint32_t ka = hr.next(tbl[w]);
-                const uint32_t kb = hr.next(tbl[w]);
+                const uint32_t ka = hr.next(tbl[c]);
+                const uint32_t kb = hr.next(tbl[c]);
                 float fa[3], na[3], fb[3], nb[3];
                 term(ka, fa, na);
                 term(kb, fb, nb);
@@ -1722,19 +1752,19 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
                 T0.add(na[0] + nb[0]); T1.add(na[1] + nb[1]); T2.add(na[2] + nb[2]);
             }
             if (cnt & 1u) {
-                float f[3], nn[3];
-                term(hr.next(tbl[w]), f, nn);
-                F0.add(f[0]); F1.add(f[1]); F2.add(f[2]);
+                float fo[3], nn[3];
+                term(hr.next(tbl[c]), fo, nn);
+                F0.add(fo[0]); F1.add(fo[1]); F2.add(fo[2]);
                 T0.add(nn[0]); T1.add(nn[1]); T2.add(nn[2]);
             }
-            const double f0 = group_total(F0.s, KAHAN ? F0.c : 0.0f, lane, n, G);
-            const double f1 = group_total(F1.s, KAHAN ? F1.c : 0.0f, lane, n, G);
-            const double f2 = group_total(F2.s, KAHAN ? F2.c : 0.0f, lane, n, G);
+            const double f0d = group_total(F0.s, KAHAN ? F0.c : 0.0f, lane, n, G);
+            const double f1d = group_total(F1.s, KAHAN ? F1.c : 0.0f, lane, n, G);
+            const double f2d = group_total(F2.s, KAHAN ? F2.c : 0.0f, lane, n, G);
             const double q0 = group_total(T0.s, KAHAN ? T0.c : 0.0f, lane, n, G);
             const double q1 = group_total(T1.s, KAHAN ? T1.c : 0.0f, lane, n, G);
             const double q2 = group_total(T2.s, KAHAN ? T2.c : 0.0f, lane, n, G);
             if (target && g == 0) {
-                const double FF[3] = {f0, f1, f2};
+                const double FF[3] = {f0d, f1d, f2d};
                 const double TT[3] = {th * q0, th * q1, th * q2};
                 err |= force_finish<float>(s, d, p, I.sp ? 1 : 0, FF, TT);
             }

@@ -50,3 +50,8 @@ def field_errors(out: dict, ref, w, x0=None) -> dict:
     if "P" in out:
         e["P"] = float(np.abs(out["P"][f] - ref.P[f]).max() / B)
     return e
+
+
+def mixed_tol(steps: int) -> float:
+    """Bar of the FP32-mixed path after `steps` steps: 1e-5 per step, 1e-3 after 100 steps."""
+    return min(1e-3, 1e-5 * max(1, int(steps)))

@@ -11,7 +11,7 @@ import pytest
 from oracle import oracle as O
 from paper_2405_03980_amd import _lib as L
 from paper_2405_03980_amd import inputs as I
-from tests._parity import field_errors, positions_ok
+from tests._parity import field_errors, mixed_tol, positions_ok
 
 pytestmark = pytest.mark.gpu
 
@@ -510,9 +510,12 @@ def test_two_particles(prec, tol):
 
 
 @pytest.mark.parametrize("visc_frac", [0.0, 1.0])
-@pytest.mark.parametrize("prec,tol", [(FP64, 1e-12), (MIXED, 1e-5)])
+@pytest.mark.parametrize("prec,tol", [(FP64, 1e-12), (MIXED, mixed_tol(5))])
 def test_single_species_mixture(visc_frac, prec, tol):
-    """No unlike pairs (S = 0 everywhere) or only viscous pairs."""
+    """No unlike pairs (S = 0 everywhere) or only viscous pairs, 5 steps.  With an
+    inviscid fluid the spins come only from the torques of the wall pairs, so the largest
+    spin is small and the normwise spin error of the FP32-mixed path, about 1e-5 after 5
+    steps, is the largest of any field here: the bar is the path's 1e-5 per step."""
     w = I.make_cylinder(12, visc_frac=visc_frac)
     ref = O.State.from_workload(w)
     ref.step(1e-4, w.Omega, 5)
