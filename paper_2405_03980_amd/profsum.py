@@ -28,8 +28,8 @@ import sys
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-BENCH = ("python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline --fp64-steps 0 --batch-steps 0 "
-         "--f1-steps 3")
+BENCH = ("python3 bench.py --steps 5 --warmup 2 --runs 1 --no-cpu-baseline --no-configs "
+         "--fp64-steps 0 --batch-steps 0 --f1-steps 3")
 COPY = "python3 bench.py --copy-calibration 1024"
 SQ = ("SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_SALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES "
       "SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_VALU")
@@ -50,9 +50,9 @@ COMMANDS = [
 VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
 COPY_MIB = 1024
 KERNEL_GROUPS = {"k_keys<float>": "keys", "k_scatter": "scatter", "k_reorder<float>": "reorder",
-                 "k_density_cand<true, false>": "density", "k_force_cand<true>": "force",
-                 "k_density_cand<true, true>": "density_flagging", "k_filter_cand<true>": "filter",
-                 "k_collide": "collide"}
+                 "k_density_cand<true, false, 32>": "density", "k_force_cand<true>": "force",
+                 "k_density_cand<true, true, 32>": "density_flagging",
+                 "k_filter_cand<true>": "filter", "k_collide": "collide"}
 
 
 def source_sha() -> str:
