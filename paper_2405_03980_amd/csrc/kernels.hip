@@ -408,21 +408,6 @@ __device__ __forceinline__ R kernel_W(int kernel, R r2, R inv_h, R wnorm)
     return wnorm * (R)0.25 * t * t * t;
 }
 
-// Running sum of FP32 terms held in FP64 (the brick sweeps' accurate sums): one conversion
-// and one FP64 add per term, where a compensated FP32 add takes four FP32 operations; on
-// CDNA the FP64 add issues at the FP32 rate.  Plain FP32 addition when WIDE is false.
-template <bool WIDE>
-struct SumF {
-    double d = 0.0;
-    float f = 0.0f;
-    __device__ __forceinline__ void add(float x)
-    {
-        if (WIDE) d += (double)x;
-        else f += x;
-    }
-    __device__ __forceinline__ double value() const { return WIDE ? d : (double)f; }
-};
-
 // Compensated (Kahan) accumulation; plain addition when KAHAN is false.
 template <typename R, bool KAHAN>
 struct Acc {
@@ -1593,7 +1578,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
             uint64_t mc;
             hit_share([&](int cc) { return mrow[cc]; }, act ? H : 0u, g, G, cnt, c, mc);
             const float4 me = stage[toff + t0 + tt];
-            SumF<KAHAN> sw, su;
+            Acc<float, KAHAN> sw, su;
             uint32_t nloc = 0;  // near hits of this lane (COLL)
             auto next_k = [&]() {
                 while (mc == 0) mc = mrow[++c];
@@ -1617,7 +1602,7 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
                 }
             };
             // a per-lane trip count (lanes leave as they finish), two hits per trip: their
-            // values are added in FP32, then into the FP64 sums
+            // values are added in FP32, then into the compensated sums
             for (uint32_t i = 1; i < cnt; i += 2) {
                 float Wa, Ua, Wb, Ub;
                 hit(Wa, Ua);
@@ -1641,8 +1626,8 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
                     s.nearq[(size_t)(pbase + t0 + tt) * kNearCap + base + j] = F.begin[sl] + (kq - F.off[sl]);
                 }
             }
-            const double SW = d->wnorm * group_total_d(sw.value(), lane, (int)ntc, G);
-            const double SU = d->wnorm * group_total_d(su.value(), lane, (int)ntc, G);
+            const double SW = d->wnorm * group_total(sw.s, KAHAN ? sw.c : 0.0f, lane, (int)ntc, G);
+            const double SU = d->wnorm * group_total(su.s, KAHAN ? su.c : 0.0f, lane, (int)ntc, G);
             if (act && g == 0) {
                 const uint32_t p = pbase + t0 + tt;
                 const uint8_t ski = SK[p];
@@ -1770,7 +1755,7 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
             const PairI I = pair_target(K, Ai, Bi, Ci);
             HitReplay hr(s.masks + (size_t)p * kMaskSlots, cellnw[c], target, g, G);
             const uint32_t cnt = hr.cnt;
-            SumF<KAHAN> F0, F1, F2, T0, T1, T2;
+            Acc<float, KAHAN> F0, F1, F2, T0, T1, T2;
             auto term = [&](uint32_t k, float fo[3], float nn[3]) {
                 const float4 A = SA[k], B = SB[k], C = SC[k];
                 pair_force_f32<KT, EQM>(K, I, A, B, C, Ai.x - A.x, Ai.y - A.y, Ai.z - A.z,
@@ -1778,7 +1763,7 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
                                         Ci.z + C.z, fo, nn);
             };
             // per-lane trip count, two hits per trip: the two terms are added in FP32, then
-            // into the FP64 sums (one FP64 add per two hits)
+            // into the compensated sums (one compensated add per two hits)
             for (uint32_t i = 1; i < cnt; i += 2) {
                 const uint32_t ka = hr.next(tbl[c]);
                 const uint32_t kb = hr.next(tbl[c]);
@@ -1794,12 +1779,12 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
                 F0.add(fo[0]); F1.add(fo[1]); F2.add(fo[2]);
                 T0.add(nn[0]); T1.add(nn[1]); T2.add(nn[2]);
             }
-            const double f0d = group_total_d(F0.value(), lane, n, G);
-            const double f1d = group_total_d(F1.value(), lane, n, G);
-            const double f2d = group_total_d(F2.value(), lane, n, G);
-            const double q0 = group_total_d(T0.value(), lane, n, G);
-            const double q1 = group_total_d(T1.value(), lane, n, G);
-            const double q2 = group_total_d(T2.value(), lane, n, G);
+            const double f0d = group_total(F0.s, KAHAN ? F0.c : 0.0f, lane, n, G);
+            const double f1d = group_total(F1.s, KAHAN ? F1.c : 0.0f, lane, n, G);
+            const double f2d = group_total(F2.s, KAHAN ? F2.c : 0.0f, lane, n, G);
+            const double q0 = group_total(T0.s, KAHAN ? T0.c : 0.0f, lane, n, G);
+            const double q1 = group_total(T1.s, KAHAN ? T1.c : 0.0f, lane, n, G);
+            const double q2 = group_total(T2.s, KAHAN ? T2.c : 0.0f, lane, n, G);
             if (target && g == 0) {
                 const double FF[3] = {f0d, f1d, f2d};
                 const double TT[3] = {th * q0, th * q1, th * q2};
@@ -1924,9 +1909,9 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_filter_cand(DevState s)
             const float Pi = RP[2 * (size_t)p + 1];
             HitReplay hr(s.masks + (size_t)p * kMaskSlots, NW, target, g, G);
             // P~ = P_i + sum V_j (P_j - P_i) W_ij / (V_i W(0) + sum V_j W_ij): the numerator
-            // holds only pressure differences (summed in FP64); the denominator's terms are all
+            // holds only pressure differences (compensated); the denominator's terms are all
             // positive and it scales only that difference, so it is summed plainly
-            SumF<KAHAN> num;
+            Acc<float, KAHAN> num;
             float den = 0.0f;
             auto hit = [&](float &nm) {
                 const uint32_t k = hr.next(tbl[w]);
@@ -1936,7 +1921,7 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_filter_cand(DevState s)
                 nm = fmaf(-A.w, Pi, SP[k]) * W;
                 den = fmaf(A.w, W, den);
             };
-            // two hits per trip, their numerator terms added in FP32 before the FP64 add
+            // two hits per trip, their numerator terms added in FP32 before the compensated add
             for (uint32_t i = 1; i < hr.cnt; i += 2) {
                 float na, nb;
                 hit(na);
@@ -1948,7 +1933,7 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_filter_cand(DevState s)
                 hit(nm);
                 num.add(nm);
             }
-            const double sn = group_total_d(num.value(), lane, n, G);
+            const double sn = group_total(num.s, KAHAN ? num.c : 0.0f, lane, n, G);
             const double sd = group_total(den, 0.0f, lane, n, G);
             if (target && g == 0) {
                 const double Vp = (double)AUX[4 * (size_t)p], Pp = (double)Pi;
