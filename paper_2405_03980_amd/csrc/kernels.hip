@@ -1683,10 +1683,12 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
         if (err) atomicOr(s.err, err);
         return;
     }
+    if (brick_own_count(F, d, bxyz) == 0) return;  // the same for the whole workgroup
+    stage_force(s, F, M, vref, d->inv_h, SA, SB, SC);
+    __syncthreads();
     // Cell w: its stencil list and fluid targets; wall targets are finished here (zero force
     // and torque), and a cell of more than 64 particles or a stencil longer than the windows
-    // is evaluated per particle by its wave.  None of this reads the staged particles, so it
-    // comes first and a brick without fluid targets stages nothing.
+    // is evaluated per particle by its wave.
     {
         const uint32_t toff = F.off[tslot], pbase = F.begin[tslot];
         const uint32_t nt = has_cell ? F.off[tslot + 1] - toff : 0u;
@@ -1716,12 +1718,6 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
     __syncthreads();
     uint32_t T = 0;
     for (int c = 0; c < 8; c++) T += (uint32_t)__popcll(tmask[c]);
-    if (T == 0) {  // the same for the whole workgroup
-        if (err) atomicOr(s.err, err);
-        return;
-    }
-    stage_force(s, F, M, vref, d->inv_h, SA, SB, SC);
-    __syncthreads();
     const uint32_t b0 = (T * (uint32_t)w) / 8u, b1 = (T * (uint32_t)(w + 1)) / 8u;
     const PairK K(d);
     const double th = -0.5 * d->h;  // torque = -(h/2) n'
