@@ -127,7 +127,7 @@ typedef struct {
                             /* cell_factor 1 on every instance (else 1 is used); 0: keep;  */
                             /* any other value is SPH_E_INVALID                            */
     int32_t xcd_run;        /* brick sweeps: consecutive bricks (in Morton order) given to   */
-                            /* each of the 8 XCDs in turn, 1..256 (default 16); 0: keep      */
+                            /* each of the 8 XCDs in turn, 1..256 (default 8); 0: keep       */
     int32_t list_targets;   /* brick density sweep: targets tested per round, 16 or 32        */
                             /* (default 32); 0: keep                                          */
 } sph_tuning;

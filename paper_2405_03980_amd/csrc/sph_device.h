@@ -101,7 +101,7 @@ struct Launch {
     int sweep = SWEEP_CAND;  // brick sweeps when every instance allows them (FP32-mixed, cf = 1)
     int list_targets = 32;   // targets per round of the brick density sweep: 16 or 32
 };
-constexpr uint32_t kDefaultXcdRun = 16;
+constexpr uint32_t kDefaultXcdRun = 8;
 
 // Launchers (kernels.hip).  All enqueue on `st` and return hipGetLastError().
 // mode 0: load/initial evaluation (no kick or drift); mode 1: time step.
