@@ -1245,7 +1245,7 @@ __device__ __forceinline__ PairI pair_target(const PairK &k, float4 A, float4 B,
 // r = r_s (units of h) = x_i - x_j, v = v_s = v_i - v_j, hs = (w_i + w_j)/2.  No branch on
 // the species: the unlike terms are selected, the viscous-viscous one vanishes through
 // I.ev and V_j taken only for a viscous neighbour (B.w = -V_j).  EQM: equal species masses.
-template <int KT, bool EQM>
+template <int KT, bool EQM, bool VISC = true>
 __device__ __forceinline__ void pair_force_f32(const PairK &k, const PairI &I, float4 A, float4 B,
                                                float4 C, float r0, float r1, float r2, float v0,
                                                float v1, float v2, float hs0, float hs1, float hs2,
@@ -1260,14 +1260,22 @@ __device__ __forceinline__ void pair_force_f32(const PairK &k, const PairI &I, f
     const float sT = fmaf(B.w * B.w, EQM ? k.ks0 : (spj ? k.ks1 : k.ks0), I.sT);
     const float gT = unl ? mF * sT : 0.0f;
     const float gm = unl ? W * fmaf(C.w, k.kC, I.cVS) : 0.0f;
-    const float gv = I.ev * (spj ? -B.w : 0.0f) * mF;
-    // u = v - hs x r; non-central part c = gm v + gv u
-    const float u0 = fmaf(hs2, r1, fmaf(-hs1, r2, v0));
-    const float u1 = fmaf(hs0, r2, fmaf(-hs2, r0, v1));
-    const float u2 = fmaf(hs1, r0, fmaf(-hs0, r1, v2));
-    const float c0 = fmaf(gm, v0, gv * u0);
-    const float c1 = fmaf(gm, v1, gv * u1);
-    const float c2 = fmaf(gm, v2, gv * u2);
+    // non-central part c = gm v + gv u, u = v - hs x r; without VISC (an inviscid target,
+    // I.ev = 0) gv is zero and c = gm v, the same value the full form gives
+    float c0, c1, c2;
+    if (VISC) {
+        const float gv = I.ev * (spj ? -B.w : 0.0f) * mF;
+        const float u0 = fmaf(hs2, r1, fmaf(-hs1, r2, v0));
+        const float u1 = fmaf(hs0, r2, fmaf(-hs2, r0, v1));
+        const float u2 = fmaf(hs1, r0, fmaf(-hs0, r1, v2));
+        c0 = fmaf(gm, v0, gv * u0);
+        c1 = fmaf(gm, v1, gv * u1);
+        c2 = fmaf(gm, v2, gv * u2);
+    } else {
+        c0 = gm * v0;
+        c1 = gm * v1;
+        c2 = gm * v2;
+    }
     const float gh = gp + gT;
     f[0] = fmaf(gh, r0, c0);
     f[1] = fmaf(gh, r1, c1);
@@ -1663,8 +1671,8 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
     __shared__ float4 SC[kStageForce];   // half the spin, V/S
     __shared__ double vref[3];
     __shared__ int16_t tbl[kBrickThreads / 64][kCandWin][64];
-    __shared__ uint64_t tmask[kBrickThreads / 64];  // fluid targets of each cell
-    __shared__ int32_t cellnw[kBrickThreads / 64];  // windows of each cell's stencil list
+    __shared__ uint64_t tmask[2][kBrickThreads / 64];  // fluid targets of each cell, by species
+    __shared__ int32_t cellnw[kBrickThreads / 64];     // windows of each cell's stencil list
     const uint32_t brick = brick_of_workgroup(blockIdx.x, gridDim.x, s.xcd_run);
     const uint32_t bxyz = s.brick_xyz[brick];
     const InstDesc *d = s.desc + s.brick_inst[brick];
@@ -1692,7 +1700,7 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
     {
         const uint32_t toff = F.off[tslot], pbase = F.begin[tslot];
         const uint32_t nt = has_cell ? F.off[tslot + 1] - toff : 0u;
-        uint64_t fl = 0;
+        uint64_t fl0 = 0, fl1 = 0;
         int nw = 0;
         if (nt) {
             const StencilList S = stencil_list(F, ts, lane, &tbl[w][0][0]);
@@ -1707,43 +1715,59 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
                     const double z[3] = {0.0, 0.0, 0.0};
                     err |= force_finish<float>(s, d, pbase + lane, sk_t & 1, z, z);
                 }
-                fl = __ballot(fluid);
+                fl0 = __ballot(fluid && !(sk_t & 1));
+                fl1 = __ballot(fluid && (sk_t & 1));
             }
         }
         if (lane == 0) {
-            tmask[w] = fl;
+            tmask[0][w] = fl0;
+            tmask[1][w] = fl1;
             cellnw[w] = nw;
         }
     }
     __syncthreads();
-    uint32_t T = 0;
-    for (int c = 0; c < 8; c++) T += (uint32_t)__popcll(tmask[c]);
-    const uint32_t b0 = (T * (uint32_t)w) / 8u, b1 = (T * (uint32_t)(w + 1)) / 8u;
+    // Flat target order: the inviscid targets of cells 0..7, then the viscous ones.  Shares
+    // are balanced by cost, an inviscid target (no viscous term) counting 7 and a viscous
+    // one 8, so that a wave whose share is all inviscid runs the shorter hit loop.
+    uint32_t TS[2] = {0u, 0u};
+    for (int c = 0; c < 8; c++) {
+        TS[0] += (uint32_t)__popcll(tmask[0][c]);
+        TS[1] += (uint32_t)__popcll(tmask[1][c]);
+    }
+    const uint32_t T = TS[0] + TS[1], C7 = 7u * TS[0], Ctot = C7 + 8u * TS[1];
+    auto share_start = [&](uint32_t ww) {
+        const uint32_t cw = (Ctot * ww) / 8u;
+        return cw <= C7 ? (cw + 6u) / 7u : TS[0] + (cw - C7 + 7u) / 8u;
+    };
+    const uint32_t b0 = share_start((uint32_t)w), b1 = share_start((uint32_t)w + 1u);
     const PairK K(d);
     const double th = -0.5 * d->h;  // torque = -(h/2) n'
     // Per block of up to 64 of the wave's targets: they share the lanes as (target, group g
     // of G).  Compiled once per smoothing kernel and for equal or unequal species masses,
     // chosen per brick (a batch may mix them), so that the hit loop carries no branch on them.
-    auto sweep = [&](auto kt, auto eqm) {
+    auto sweep = [&](auto kt, auto eqm, auto visc) {
         constexpr int KT = decltype(kt)::value;
         constexpr bool EQM = decltype(eqm)::value;
+        constexpr bool VISC = decltype(visc)::value;
         for (uint32_t f0 = b0; f0 < b1; f0 += 64) {
             const int n = (int)min(64u, b1 - f0);
             const int G = 64 / n;
             const int g = lane / n;
             const bool target = g < G;
-            // this lane's target: flat index f, the rank-th fluid target of cell c
+            // this lane's target: flat index f, the rank-th target of species sp in cell c
             const uint32_t f = f0 + (uint32_t)(lane % n);
+            const int sp = f < TS[0] ? 0 : 1;
+            const uint32_t fs = sp ? f - TS[0] : f;
             int c = 0;
             uint32_t rank = 0, before = 0;
             for (int cc = 0; cc < 8; cc++) {
-                if (f >= before) {
+                if (fs >= before) {
                     c = cc;
-                    rank = f - before;
+                    rank = fs - before;
                 }
-                before += (uint32_t)__popcll(tmask[cc]);
+                before += (uint32_t)__popcll(tmask[sp][cc]);
             }
-            const uint32_t local = (uint32_t)__builtin_ctzll(drop_low_bits(tmask[c], rank));
+            const uint32_t local = (uint32_t)__builtin_ctzll(drop_low_bits(tmask[sp][c], rank));
             const int cs = slot_index(1 + (c & 1), 1 + ((c >> 1) & 1), 1 + (c >> 2));
             const uint32_t p = F.begin[cs] + local;
             const uint32_t ki = F.off[cs] + local;
@@ -1754,9 +1778,9 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
             Acc<float, KAHAN> F0, F1, F2, T0, T1, T2;
             auto term = [&](uint32_t k, float fo[3], float nn[3]) {
                 const float4 A = SA[k], B = SB[k], C = SC[k];
-                pair_force_f32<KT, EQM>(K, I, A, B, C, Ai.x - A.x, Ai.y - A.y, Ai.z - A.z,
-                                        Bi.x - B.x, Bi.y - B.y, Bi.z - B.z, Ci.x + C.x, Ci.y + C.y,
-                                        Ci.z + C.z, fo, nn);
+                pair_force_f32<KT, EQM, VISC>(K, I, A, B, C, Ai.x - A.x, Ai.y - A.y, Ai.z - A.z,
+                                              Bi.x - B.x, Bi.y - B.y, Bi.z - B.z, Ci.x + C.x,
+                                              Ci.y + C.y, Ci.z + C.z, fo, nn);
             };
             // per-lane trip count, two hits per trip: the two terms are added in FP32, then
             // into the compensated sums (one compensated add per two hits)
@@ -1792,13 +1816,26 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
     using Cub = std::integral_constant<int, KERNEL_CUBIC>;
     using Eq = std::integral_constant<bool, true>;
     using Uneq = std::integral_constant<bool, false>;
+    using Visc = std::integral_constant<bool, true>;
+    using Inv = std::integral_constant<bool, false>;
     const bool eq = d->mass[0] == d->mass[1];
+    const bool inv = b1 <= TS[0];  // the wave's share holds inviscid targets only
     if (d->kernel == KERNEL_WENDLAND) {
-        if (eq) sweep(Wend(), Eq());
-        else sweep(Wend(), Uneq());
+        if (eq) {
+            if (inv) sweep(Wend(), Eq(), Inv());
+            else sweep(Wend(), Eq(), Visc());
+        } else {
+            if (inv) sweep(Wend(), Uneq(), Inv());
+            else sweep(Wend(), Uneq(), Visc());
+        }
     } else {
-        if (eq) sweep(Cub(), Eq());
-        else sweep(Cub(), Uneq());
+        if (eq) {
+            if (inv) sweep(Cub(), Eq(), Inv());
+            else sweep(Cub(), Eq(), Visc());
+        } else {
+            if (inv) sweep(Cub(), Uneq(), Inv());
+            else sweep(Cub(), Uneq(), Visc());
+        }
     }
     if (err) atomicOr(s.err, err);
 }
