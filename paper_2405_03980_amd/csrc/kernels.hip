@@ -1610,7 +1610,9 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
                 }
             };
             // a per-lane trip count (lanes leave as they finish), two hits per trip: their
-            // values are added in FP32, then into the compensated sums
+            // values are added in FP32, then into the compensated sums; the loop body is
+            // unrolled twice (0.05 ms faster here, 0.1 ms slower in the force sweep)
+#pragma unroll 2
             for (uint32_t i = 1; i < cnt; i += 2) {
                 float Wa, Ua, Wb, Ub;
                 hit(Wa, Ua);
