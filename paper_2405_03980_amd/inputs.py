@@ -182,11 +182,13 @@ def make_cylinder(nz: int, *, seed=(3980, 1), kernel: int = KERNEL_WENDLAND_C2,
 
 def make_cluster(n_side: int = 8, *, seed=(3980, 9), kernel: int = KERNEL_WENDLAND_C2,
                  visc_frac: float = 0.5, noise: float = 1e-2, spin: float = 0.5,
-                 jitter: float = 0.1, c0: float = 2.0) -> Workload:
+                 jitter: float = 0.1, c0: float = 2.0, h_factor: float = 1.3) -> Workload:
     """A free, wall-free cluster in an open domain, for conservation checks.
 
     Jittered cubic lattice of n_side^3 particles in the middle of a box three times its
-    size; random velocities and spins so that every pair term is active.
+    size; random velocities and spins so that every pair term is active.  With
+    h_factor = 2 the cells (edge 2h = 4 dx) hold 4^3 lattice points each, and a cluster of
+    8^3 fills exactly the 2x2x2 cells of one brick.
     """
     rng = np.random.default_rng(list(seed))
     dx = 1.0 / (3 * n_side)
@@ -198,7 +200,8 @@ def make_cluster(n_side: int = 8, *, seed=(3980, 9), kernel: int = KERNEL_WENDLA
     species = _assign_species(rng, n, visc_frac)
     v = rng.normal(0.0, noise, size=(3, n))
     omega = rng.normal(0.0, spin, size=(3, n))
-    params = base_params(kernel, GEOM_OPEN, dx, [0.0, 0.0, 0.0], [1.0, 1.0, 1.0], c0)
+    params = base_params(kernel, GEOM_OPEN, dx, [0.0, 0.0, 0.0], [1.0, 1.0, 1.0], c0,
+                         h_factor=h_factor)
     kind = np.zeros(n, dtype=np.uint8)
     return Workload(f"cluster{n_side}", params, x, v, omega, species, kind)
 

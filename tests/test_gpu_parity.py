@@ -411,6 +411,36 @@ def test_brick_fallback_when_cells_are_full(h_factor):
     s.close()
 
 
+@pytest.mark.parametrize("visc_frac", [0.0, 0.5, 1.0])
+def test_brick_of_512_targets(visc_frac):
+    """One brick alone in an open domain, its eight cells holding 64 particles each (an 8^3
+    cluster with h = 2 dx): every cell is taken from the stage, the force sweep's waves get
+    shares of up to 69 targets (two rounds of lanes) with either species, all inviscid
+    waves or all viscous ones, and every field matches the oracle initially and after a
+    step."""
+    w = I.make_cluster(8, h_factor=2.0, visc_frac=visc_frac)
+    h, x = w.params["h"], w.x
+    cells = np.floor(x / (2.0 * h)).astype(int)
+    assert np.all((cells >= 2) & (cells <= 3)), "the cluster must fill exactly one brick"
+    counts = np.bincount((cells[0] - 2) + 2 * (cells[1] - 2) + 4 * (cells[2] - 2), minlength=8)
+    assert np.all(counts == 64), counts
+    print(f"[brick512] visc_frac={visc_frac} n={w.n}", flush=True)
+    ref = O.State.from_workload(w)
+    s = _sim(w, MIXED, sweep=3)
+    e = field_errors(s.read(), ref, w)
+    print("initial", e, flush=True)
+    for k in ("rho", "P", "acc", "alpha"):
+        assert e[k] < 1e-5, (k, e[k])
+    ref.step(1e-4, w.Omega, 1)
+    s.step(1e-4, w.Omega, 1)
+    e = field_errors(s.read(), ref, w)
+    print("one step", e, flush=True)
+    assert positions_ok(e, 1e-5, 1), e
+    for k in ("v", "omega", "rho", "P"):
+        assert e[k] < 1e-5, (k, e[k])
+    s.close()
+
+
 @pytest.mark.parametrize("prec,sweep", [(FP64, None), (MIXED, 1), (MIXED, 3)])
 def test_overfull_cell_is_a_capacity_error(prec, sweep):
     """1,100 particles gathered in one cell (more than the 1,024 the search walks): the
