@@ -1872,11 +1872,15 @@ __device__ __forceinline__ void stage_filter(const DevState &s, const BrickFrame
 }
 
 // Pressure filter over the brick sweeps' neighbour masks (the density sweep's, replayed as
-// in the force sweep): lanes = (target, group g of G) over the block's fluid and
-// inner-wall targets; outer walls copy their fixed pressure directly.  The kernel shape
-// sums are scaled by the normalisation in FP64, where the self term joins the denominator;
-// the stage capacity is the force sweep's, so a brick the density sweep could not stage
-// (and left without masks) is filtered per particle here too.
+// in the force sweep).  Each wave first builds its cell's stencil list, copies the fixed
+// pressure of the cell's outer walls, and marks its targets (fluid and inner walls); a cell
+// of more than 64 particles or with a stencil longer than the windows is filtered per
+// particle by its wave.  After a barrier the brick's targets, in cell order, are dealt to
+// the eight waves in equal contiguous shares with lanes = (target, group g of G), as in
+// the force sweep.  The kernel shape sums are scaled by the normalisation in FP64, where
+// the self term joins the denominator; the stage capacity is the force sweep's, so a brick
+// the density sweep could not stage (and left without masks) is filtered per particle here
+// too.
 template <bool KAHAN>
 __global__ void __launch_bounds__(kBrickThreads, 4) k_filter_cand(DevState s)
 {
@@ -1884,6 +1888,8 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_filter_cand(DevState s)
     __shared__ float4 SA[kStageForce];  // position (brick frame), source volume
     __shared__ float SP[kStageForce];   // source volume times pressure
     __shared__ int16_t tbl[kBrickThreads / 64][kCandWin][64];
+    __shared__ uint64_t tmask[kBrickThreads / 64];  // filter targets of each cell
+    __shared__ int32_t cellnw[kBrickThreads / 64];  // windows of each cell's stencil list
     const uint32_t brick = brick_of_workgroup(blockIdx.x, gridDim.x, s.xcd_run);
     const uint32_t bxyz = s.brick_xyz[brick];
     const InstDesc *d = s.desc + s.brick_inst[brick];
@@ -1909,47 +1915,68 @@ __global__ void __launch_bounds__(kBrickThreads, 4) k_filter_cand(DevState s)
     }
     stage_filter(s, F, M, d->inv_h, SA, SP);
     __syncthreads();
-    if (!has_cell) return;
-    const uint32_t toff = F.off[tslot], pbase = F.begin[tslot];
-    const uint32_t nt = F.off[tslot + 1] - toff;
-    if (nt == 0) return;
-    const StencilList S = stencil_list(F, ts, lane, &tbl[w][0][0]);
-    if (S.NW > (uint32_t)kCandWin) {
-        for (uint32_t i = lane; i < nt; i += 64) err |= filter_one<float, KAHAN>(s, d, pbase + i);
-        if (err) atomicOr(s.err, err);
-        return;
+    {
+        const uint32_t pbase = F.begin[tslot];
+        const uint32_t nt = has_cell ? F.off[tslot + 1] - F.off[tslot] : 0u;
+        uint64_t tm = 0;
+        int nw = 0;
+        if (nt) {
+            const StencilList S = stencil_list(F, ts, lane, &tbl[w][0][0]);
+            if (S.NW > (uint32_t)kCandWin || nt > 64u) {
+                for (uint32_t i = lane; i < nt; i += 64) err |= filter_one<float, KAHAN>(s, d, pbase + i);
+            } else {
+                nw = (int)S.NW;
+                uint32_t sk_t = 0;
+                if ((uint32_t)lane < nt) sk_t = SK[pbase + lane];
+                const bool tgt = (uint32_t)lane < nt && (sk_t >> 1) != KIND_WALL_OUTER;
+                if ((uint32_t)lane < nt && !tgt) {
+                    const uint32_t q = pbase + lane;
+                    PF[q] = RP[2 * (size_t)q + 1];
+                }
+                tm = __ballot(tgt);
+            }
+        }
+        if (lane == 0) {
+            tmask[w] = tm;
+            cellnw[w] = nw;
+        }
     }
-    const int NW = (int)S.NW;
+    __syncthreads();
+    uint32_t T = 0;
+    for (int c = 0; c < 8; c++) T += (uint32_t)__popcll(tmask[c]);
+    const uint32_t b0 = (T * (uint32_t)w) / 8u, b1 = (T * (uint32_t)(w + 1)) / 8u;
     const double wn = d->wnorm, W0 = d->W0;
     auto sweep = [&](auto kt) {
         constexpr int KT = decltype(kt)::value;
-        for (uint32_t t0 = 0; t0 < nt; t0 += 64) {
-            const uint32_t nb = min(64u, nt - t0);
-            uint32_t sk_t = 0;
-            if ((uint32_t)lane < nb) sk_t = SK[pbase + t0 + lane];
-            const bool tgt = (uint32_t)lane < nb && (sk_t >> 1) != KIND_WALL_OUTER;
-            const uint64_t Mt = __ballot(tgt);
-            if ((uint32_t)lane < nb && !tgt) {
-                const uint32_t q = pbase + t0 + lane;
-                PF[q] = RP[2 * (size_t)q + 1];
-            }
-            if (Mt == 0) continue;
-            const int n = __popcll(Mt);
+        for (uint32_t f0 = b0; f0 < b1; f0 += 64) {
+            const int n = (int)min(64u, b1 - f0);
             const int G = 64 / n;
             const int g = lane / n;
             const bool target = g < G;
-            const uint32_t t = (uint32_t)__builtin_ctzll(drop_low_bits(Mt, (uint32_t)(lane % n)));
-            const uint32_t p = pbase + t0 + t;
-            const float4 Ai = SA[toff + t0 + t];
+            // this lane's target: flat index f, the rank-th target of cell c
+            const uint32_t f = f0 + (uint32_t)(lane % n);
+            int c = 0;
+            uint32_t rank = 0, before = 0;
+            for (int cc = 0; cc < 8; cc++) {
+                if (f >= before) {
+                    c = cc;
+                    rank = f - before;
+                }
+                before += (uint32_t)__popcll(tmask[cc]);
+            }
+            const uint32_t local = (uint32_t)__builtin_ctzll(drop_low_bits(tmask[c], rank));
+            const int cs = slot_index(1 + (c & 1), 1 + ((c >> 1) & 1), 1 + (c >> 2));
+            const uint32_t p = F.begin[cs] + local;
+            const float4 Ai = SA[F.off[cs] + local];
             const float Pi = RP[2 * (size_t)p + 1];
-            HitReplay hr(s.masks + (size_t)p * kMaskSlots, NW, target, g, G);
+            HitReplay hr(s.masks + (size_t)p * kMaskSlots, cellnw[c], target, g, G);
             // P~ = P_i + sum V_j (P_j - P_i) W_ij / (V_i W(0) + sum V_j W_ij): the numerator
             // holds only pressure differences (compensated); the denominator's terms are all
             // positive and it scales only that difference, so it is summed plainly
             Acc<float, KAHAN> num;
             float den = 0.0f;
             auto hit = [&](float &nm) {
-                const uint32_t k = hr.next(tbl[w]);
+                const uint32_t k = hr.next(tbl[c]);
                 const float4 A = SA[k];
                 const float d0 = Ai.x - A.x, d1 = Ai.y - A.y, d2 = Ai.z - A.z;
                 const float W = shape_W<KT>(d0 * d0 + d1 * d1 + d2 * d2);
