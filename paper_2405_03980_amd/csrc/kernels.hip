@@ -1659,11 +1659,12 @@ __global__ void __launch_bounds__(kBrickThreads) k_density_cand(DevState s)
     if (err) atomicOr(s.err, err);
 }
 
-// The fluid targets of a brick, in cell order, are dealt to its eight waves in equal
-// contiguous shares, so that the waves finish together whatever the cells' populations (a
-// workgroup holds its LDS until its last wave ends, and on a lattice the cells of one brick
-// hold 8 to 27 particles).  Each wave builds its own cell's stencil list first; a target
-// then replays its masks through the list of its own cell.
+// The fluid targets of a brick (the inviscid ones, then the viscous ones, each in cell
+// order) are dealt to its eight waves in contiguous shares of equal cost, so that the waves
+// finish together whatever the cells' populations (a workgroup holds its LDS until its last
+// wave ends, and on a lattice the cells of one brick hold 8 to 27 particles).  Each wave
+// builds its own cell's stencil list first; a target then replays its masks through the
+// list of its own cell.
 template <bool KAHAN>
 __global__ void __launch_bounds__(kBrickThreads, 4) k_force_cand(DevState s)
 {
