@@ -196,8 +196,11 @@ struct Plan {
     std::vector<InstDesc> desc;
     uint32_t N = 0, C = 0, n_waves = 0;
     uint32_t n_bricks = 0;  // 0 unless every instance has cell_factor 1
+    std::vector<uint32_t> bxyz, binst;  // the bricks: packed coordinates and instance
     bool any_filter = false, any_coll = false;
 };
+
+void brick_tables(const Plan &pl, std::vector<uint32_t> &xyz, std::vector<uint32_t> &inst);
 
 sph_status plan(int32_t n_inst, const sph_params *params, const int64_t *counts, Plan &pl,
                 std::string &msg)
@@ -246,6 +249,14 @@ sph_status plan(int32_t n_inst, const sph_params *params, const int64_t *counts,
         d.coll_rc = p->coll_alpha * p->dx;
         d.coll_rc2 = d.coll_rc * d.coll_rc;
         d.coll_e1 = 1.0 + p->coll_e;
+        // the cylinder about the z axis inscribed in the box's x-y extent, with a relative
+        // margin of 1e-4 on the squared radius: no particle of a cylinder instance may
+        // leave it, so bricks wholly outside it are left out of the brick sweeps
+        d.rxy2 = INFINITY;
+        if (p->geometry == SPH_GEOM_CYLINDER_Z) {
+            const double r = fmin(fmin(-p->lo[0], p->hi[0]), fmin(-p->lo[1], p->hi[1]));
+            if (r > 0.0) d.rxy2 = r * r * (1.0 + 1e-4);
+        }
         d.pfilter = p->pressure_filter;
         d.coll = p->coll_alpha > 0.0 ? 1 : 0;
         pl.any_filter = pl.any_filter || d.pfilter;
@@ -275,6 +286,10 @@ sph_status plan(int32_t n_inst, const sph_params *params, const int64_t *counts,
         NB += (uint64_t)((d.n[0] + 1) / 2) * ((d.n[1] + 1) / 2) * ((d.n[2] + 1) / 2);
     }
     pl.n_bricks = bricks ? (uint32_t)NB : 0u;
+    if (pl.n_bricks) {
+        brick_tables(pl, pl.bxyz, pl.binst);
+        pl.n_bricks = (uint32_t)pl.bxyz.size();
+    }
     return SPH_OK;
 }
 
@@ -320,8 +335,15 @@ void brick_tables(const Plan &pl, std::vector<uint32_t> &xyz, std::vector<uint32
                 for (uint32_t x = 0; x < nb[0]; x++)
                     keys.push_back(((uint64_t)morton3_host(x, y, z) << 32) | (x | (y << 10) | (z << 20)));
         std::sort(keys.begin(), keys.end());
+        const double ex = 2.0 * d.edge[0], ey = 2.0 * d.edge[1];
         for (uint64_t k : keys) {
-            xyz.push_back((uint32_t)(k & 0xffffffffu));
+            const uint32_t v = (uint32_t)(k & 0xffffffffu);
+            // a brick whose x-y footprint lies wholly outside the cylinder holds no particle
+            const double x0 = d.lo[0] + (double)(v & 1023u) * ex;
+            const double y0 = d.lo[1] + (double)((v >> 10) & 1023u) * ey;
+            const double cx = fmin(fmax(0.0, x0), x0 + ex), cy = fmin(fmax(0.0, y0), y0 + ey);
+            if (cx * cx + cy * cy > d.rxy2) continue;
+            xyz.push_back(v);
             inst.push_back((uint32_t)i);
         }
     }
@@ -484,7 +506,10 @@ sph_status status_of_flags(uint32_t f, std::string &msg)
 {
     if (f & ERR_INPUT) { msg = "invalid species/kind values in the particle input"; return SPH_E_INVALID; }
     if (f & ERR_NONFINITE) { msg = "non-finite value in the particle state"; return SPH_E_NONFINITE; }
-    if (f & ERR_DOMAIN) { msg = "a particle left the cell grid along a bounded axis"; return SPH_E_DOMAIN; }
+    if (f & ERR_DOMAIN) {
+        msg = "a particle left the cell grid along a bounded axis, or the cylinder of a cylinder instance";
+        return SPH_E_DOMAIN;
+    }
     if (f & ERR_CAPACITY) { msg = "a cell holds more particles than the search supports"; return SPH_E_CAPACITY; }
     return SPH_OK;
 }
@@ -670,9 +695,9 @@ sph_status sph_batch_create(int32_t n_inst, const sph_params *params, const int6
     b->ds.any_filter = pl.any_filter ? 1 : 0;
     b->ds.any_coll = pl.any_coll ? 1 : 0;
     b->ds.xcd_run = kDefaultXcdRun;
-    std::vector<uint32_t> rank_of_lin, xyz, bxyz, binst;
+    std::vector<uint32_t> rank_of_lin, xyz;
+    const std::vector<uint32_t> &bxyz = pl.bxyz, &binst = pl.binst;
     cell_tables(pl, rank_of_lin, xyz);
-    brick_tables(pl, bxyz, binst);
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMemcpyAsync(b->ds.desc, pl.desc.data(), sizeof(InstDesc) * n_inst, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->ds.steptab, b->steptab.data(), sizeof(StepParams) * n_inst, hipMemcpyHostToDevice, b->stream);

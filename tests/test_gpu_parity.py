@@ -354,6 +354,39 @@ def test_domain_exit_is_reported():
     s.close()
 
 
+@pytest.mark.parametrize("prec", [FP64, MIXED])
+def test_leaving_the_cylinder_is_reported(prec):
+    """A cylinder instance's particles stay inside the cylinder inscribed in the box's x-y
+    extent, which lets the brick sweeps leave out the bricks outside it.  A fluid particle
+    placed in a corner of the box (inside the box, outside the cylinder) is a domain error
+    at the first evaluation; one moving there is reported after the step that takes it."""
+    w = I.make_cylinder(14)
+    f = int(np.nonzero(w.kind == I.FLUID)[0][0])
+    x = w.x.copy()
+    x[0, f], x[1, f] = 0.95, 0.95  # radius 1.34 > 1, in the box [-1, 1]^2
+    from paper_2405_03980_amd import sim as S
+    s = S.Simulation(w.params, w.n, precision=prec)
+    with pytest.raises(L.SphError) as e:
+        s.init(x, w.v, w.omega, w.species, w.kind)
+        s.sync()
+    assert e.value.status == L.E_DOMAIN, e.value
+    s.close()
+    # moving out: the outermost fluid particle on the diagonal, sent in one step to
+    # (0.9, 0.9), inside the box and outside the cylinder
+    x, v = w.x.copy(), w.v.copy()
+    r = np.hypot(x[0], x[1])
+    diag = (w.kind == I.FLUID) & (x[0] > 0) & (np.abs(x[0] - x[1]) < 2 * w.params["dx"])
+    f = int(np.argmax(np.where(diag, r, -1.0)))
+    dt = 1e-4
+    v[0, f], v[1, f], v[2, f] = (0.9 - x[0, f]) / dt, (0.9 - x[1, f]) / dt, 0.0
+    s = _sim(I.Workload(w.name, w.params, x, v, w.omega, w.species, w.kind), prec)
+    s.step(dt, w.Omega, 1)
+    with pytest.raises(L.SphError) as e:
+        s.read()
+    assert e.value.status == L.E_DOMAIN
+    s.close()
+
+
 def test_invalid_species_is_reported():
     w = I.make_cylinder(10)
     w.species[w.kind != I.FLUID] = 0   # walls must be viscous
