@@ -62,10 +62,10 @@ typedef enum { SPH_FP64 = 0, SPH_FP32_MIXED = 1 } sph_precision;
 /* SPH_GEOM_PERIODIC_BOX: all three axes periodic on [lo, hi).
  * SPH_GEOM_CYLINDER_Z:   x and y bounded (walls are particles), z periodic on
  *                        [lo[2], hi[2]) (the paper's slip top and bottom, Sec. 3).  Every
- *                        particle stays inside the cylinder about the z axis inscribed in
- *                        the box's x-y extent, radius r = min(-lo[0], hi[0], -lo[1], hi[1])
- *                        (x^2 + y^2 <= r^2 (1 + 1e-4)); a particle outside it is a domain
- *                        error (SPH_E_DOMAIN), like one that leaves the box.
+ *                        particle stays within 2h of the cylinder about the z axis
+ *                        inscribed in the box's x-y extent: x^2 + y^2 <= (r + 2h)^2,
+ *                        r = min(-lo[0], hi[0], -lo[1], hi[1]).  A particle beyond is a
+ *                        domain error (SPH_E_DOMAIN), like one that leaves the box.
  * SPH_GEOM_OPEN:         no periodic axis (free clusters). */
 typedef enum { SPH_GEOM_PERIODIC_BOX = 0, SPH_GEOM_CYLINDER_Z = 1, SPH_GEOM_OPEN = 2 } sph_geometry;
 

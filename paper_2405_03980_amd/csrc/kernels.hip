@@ -224,7 +224,7 @@ __global__ void k_keys(DevState s, int mode, double kick, double dt)
     int c0 = cell_coord(d, 0, xo[0], err);
     int c1 = cell_coord(d, 1, xo[1], err);
     int c2 = cell_coord(d, 2, xo[2], err);
-    if (xo[0] * xo[0] + xo[1] * xo[1] > d->rxy2) err |= ERR_DOMAIN;  // left the cylinder
+    if (xo[0] * xo[0] + xo[1] * xo[1] > d->rxy2) err |= ERR_DOMAIN;  // beyond the cylinder
     uint32_t lin = (uint32_t)c0 + (uint32_t)d->n[0] * ((uint32_t)c1 + (uint32_t)d->n[1] * (uint32_t)c2);
     uint32_t key = s.rank_of_lin[d->cell_off + lin];
     s.key[p] = key;

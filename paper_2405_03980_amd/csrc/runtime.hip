@@ -249,13 +249,14 @@ sph_status plan(int32_t n_inst, const sph_params *params, const int64_t *counts,
         d.coll_rc = p->coll_alpha * p->dx;
         d.coll_rc2 = d.coll_rc * d.coll_rc;
         d.coll_e1 = 1.0 + p->coll_e;
-        // the cylinder about the z axis inscribed in the box's x-y extent, with a relative
-        // margin of 1e-4 on the squared radius: no particle of a cylinder instance may
-        // leave it, so bricks wholly outside it are left out of the brick sweeps
+        // the cylinder about the z axis inscribed in the box's x-y extent, widened by the
+        // kernel support 2h (fluid pressed into the wall layers may pass the outermost one
+        // by a fraction of dx): no particle of a cylinder instance may leave it, so bricks
+        // wholly outside it are left out of the brick sweeps
         d.rxy2 = INFINITY;
         if (p->geometry == SPH_GEOM_CYLINDER_Z) {
             const double r = fmin(fmin(-p->lo[0], p->hi[0]), fmin(-p->lo[1], p->hi[1]));
-            if (r > 0.0) d.rxy2 = r * r * (1.0 + 1e-4);
+            if (r > 0.0) d.rxy2 = (r + 2.0 * p->h) * (r + 2.0 * p->h);
         }
         d.pfilter = p->pressure_filter;
         d.coll = p->coll_alpha > 0.0 ? 1 : 0;

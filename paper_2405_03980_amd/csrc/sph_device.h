@@ -33,7 +33,8 @@ struct InstDesc {
     double coll_rc, coll_rc2;   // collision step: distance coll_alpha dx and its square
     double coll_e1;             // 1 + restitution
     double rxy2;                // cylinder geometry: x^2 + y^2 of every particle stays within
-                                // rxy2, the inscribed cylinder about the z axis (+inf else)
+                                // rxy2 (the inscribed cylinder about the z axis widened by
+                                // 2h); +inf for the other geometries
     int32_t pfilter, coll;      // pressure filter on; collision step on
     int32_t n[3], periodic[3];
     int32_t cf, kernel;

@@ -356,10 +356,11 @@ def test_domain_exit_is_reported():
 
 @pytest.mark.parametrize("prec", [FP64, MIXED])
 def test_leaving_the_cylinder_is_reported(prec):
-    """A cylinder instance's particles stay inside the cylinder inscribed in the box's x-y
-    extent, which lets the brick sweeps leave out the bricks outside it.  A fluid particle
-    placed in a corner of the box (inside the box, outside the cylinder) is a domain error
-    at the first evaluation; one moving there is reported after the step that takes it."""
+    """A cylinder instance's particles stay within 2h of the cylinder inscribed in the box's
+    x-y extent, which lets the brick sweeps leave out the bricks beyond it.  A fluid
+    particle placed in a corner of the box (inside the box, beyond the cylinder) is a domain
+    error at the first evaluation; one moving there is reported after the step that takes
+    it."""
     w = I.make_cylinder(14)
     f = int(np.nonzero(w.kind == I.FLUID)[0][0])
     x = w.x.copy()
